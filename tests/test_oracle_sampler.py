@@ -1,0 +1,130 @@
+"""Pins of the oracle's complete sampler (Gibbs proposal + MH) against exact
+results of the target model.
+
+* exact enumeration: the final states of many independent chains follow the
+  Boltzmann distribution of the periodic Ising model (chi-square over all
+  2^9 states at L=3), both for the exact App. C kernel of a *different*
+  temperature (so that the MH correction is what makes it right) and for
+  random filters; the same test against the proposal's own temperature must
+  fail, which shows the test can see a missing or wrong correction;
+* exact finite-lattice <E> and specific heat from a row transfer matrix
+  (L = 4, 6) against the chain accumulators;
+* with the exact kernel at the target temperature, log r is zero up to the
+  float32 rounding of the kernel, so nearly every proposal is accepted.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import exact_ising as X  # noqa: E402
+
+from paper_2008_05401_amd import workloads as WL  # noqa: E402
+
+
+def _final_state_hist(orc, f, L, T, n_chains, n_sweeps, seed):
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    ch = orc.Chains(m, orc.ISING, L, np.full(n_chains, T), seed=seed)
+    ch.run(n_sweeps)
+    idx = X.state_index(ch.state[:, 0])
+    return np.bincount(idx, minlength=2 ** (L * L)).astype(np.float64), ch
+
+
+def test_mh_corrects_mismatched_exact_kernel(orc):
+    L, T, Tprop = 3, 2.0, 3.0
+    f = WL.analytic_ising_filters(Tprop)
+    counts, ch = _final_state_hist(orc, f, L, T, 20000, 40, seed=1)
+    states = X.all_states(L)
+    chi2, dof, p = X.chi2_pvalue(counts, X.boltzmann_weights(states, T))
+    assert p > 1e-4, (chi2, dof)
+    # the uncorrected proposal distribution is detectably different
+    _, _, p_wrong = X.chi2_pvalue(counts, X.boltzmann_weights(states, Tprop))
+    assert p_wrong < 1e-8
+    acc = ch.rec["n_acc"].sum() / ch.rec["sweeps"].sum()
+    assert 0.05 < acc < 0.98
+    assert ch.ties[0] == 0
+
+
+def _exact_samples(L, T, n, seed):
+    states = X.all_states(L)
+    p = X.boltzmann_weights(states, T)
+    idx = np.random.default_rng(seed).choice(len(p), size=n, p=p)
+    return states[idx][:, None].copy(), p
+
+
+def test_mh_with_random_filters_keeps_boltzmann(orc):
+    # random proposals mix slowly from a far start; starting from exact samples,
+    # a correct MH kernel must leave the Boltzmann distribution unchanged
+    L, T = 3, 2.5
+    f = WL.random_filters_with_bias(2, 1, 2, 0.6, 0.4, seed=21)
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    s0, p = _exact_samples(L, T, 20000, seed=8)
+    ch = orc.Chains(m, orc.ISING, L, np.full(20000, T), seed=2, state=s0)
+    ch.run(30)
+    counts = np.bincount(X.state_index(ch.state[:, 0]), minlength=2 ** (L * L)).astype(np.float64)
+    chi2, dof, pv = X.chi2_pvalue(counts, p)
+    assert pv > 1e-4, (chi2, dof)
+    acc = ch.rec["n_acc"].sum() / ch.rec["sweeps"].sum()
+    assert acc > 0.1
+    assert ch.ties[0] == 0
+
+
+def test_mh_with_wide_filters_and_two_gibbs_steps(orc):
+    # K=4, Lw=3 on L=3 (the filter covers the whole lattice) and gibbs_k=2
+    L, T = 3, 2.2
+    f = WL.random_filters_with_bias(4, 1, 3, 0.3, 0.2, seed=5)
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    s0, p = _exact_samples(L, T, 20000, seed=9)
+    ch = orc.Chains(m, orc.ISING, L, np.full(20000, T), seed=9, gibbs_k=2, state=s0)
+    ch.run(30)
+    counts = np.bincount(X.state_index(ch.state[:, 0]), minlength=512).astype(np.float64)
+    chi2, dof, pv = X.chi2_pvalue(counts, p)
+    assert pv > 1e-4, (chi2, dof)
+    acc = ch.rec["n_acc"].sum() / ch.rec["sweeps"].sum()
+    assert acc > 0.05
+
+
+@pytest.mark.parametrize("L,T", [(4, 2.269), (6, 2.269), (6, 3.0)])
+def test_accumulators_match_transfer_matrix(orc, L, T):
+    g = X.dos_transfer(L)
+    e1, e2, c_exact = X.thermo(g, L, T)
+    f = WL.analytic_ising_filters(T)
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    n, burn, meas = 256, 100, 400
+    ch = orc.Chains(m, orc.ISING, L, np.full(n, T), seed=3, burnin=burn)
+    ch.run(burn + meas)
+    r = ch.rec
+    assert np.all(r["n_meas"] == meas)
+    mE = r["sumE"] / meas
+    mE2 = r["sumE2"] / meas
+    # independent chains: the spread of per-chain means gives the error
+    se = mE.std(ddof=1) / np.sqrt(n)
+    assert abs(mE.mean() - e1) < 5 * se + 1e-12, (mE.mean(), e1, se)
+    beta = 1.0 / T
+    c_chain = beta * beta * (mE2 - mE * mE) / (L * L)
+    # per-chain C is biased low by a factor ~(1 - tau/meas); pool over chains instead
+    c_pool = beta * beta * (mE2.mean() - mE.mean() ** 2) / (L * L)
+    G = 32  # delete-one-group jackknife over groups of chains
+    grp = np.arange(n) % G
+    jack = np.array([beta * beta * (mE2[grp != i].mean() - mE[grp != i].mean() ** 2) / (L * L)
+                     for i in range(G)])
+    se_c = np.sqrt((G - 1) / G * ((jack - jack.mean()) ** 2).sum())
+    assert abs(c_pool - c_exact) < 5 * se_c + 0.02 * c_exact, (c_pool, c_exact, se_c)
+    assert np.all(c_chain >= 0)
+    acc = r["n_acc"].sum() / r["sweeps"].sum()
+    assert acc > 0.99
+
+
+def test_run_is_resumable_bitwise(orc):
+    L, T = 6, 2.5
+    f = WL.random_filters_with_bias(4, 1, 3, 0.4, 0.2, seed=7)
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    a = orc.Chains(m, orc.ISING, L, np.linspace(2.0, 3.0, 8), seed=4, burnin=5)
+    a.run(30)
+    b = orc.Chains(m, orc.ISING, L, np.linspace(2.0, 3.0, 8), seed=4, burnin=5)
+    b.run(12)
+    b.run(18)
+    assert np.array_equal(a.state, b.state)
+    assert a.rec.tobytes() == b.rec.tobytes()
