@@ -1,0 +1,193 @@
+/*
+ * crbm.h -- C ABI of the MI355X (gfx950) hot path of convolutional-RBM-aided
+ * Monte Carlo (Alcalde Puente & Eremin, arXiv:2008.05401).
+ *
+ * The library samples P(x) ~ exp(-beta E(x)) on an L x L periodic lattice
+ * with many independent Markov chains.  One "sweep" of a chain is
+ *   1. gibbs_k block-Gibbs steps v -> h -> v' of the CRBM (App. B, Gibbs
+ *      sampling; conditionals P(h|v), P(v|h) of the convolutional energy
+ *      Eq. (energy_CRBM)), which propose x';
+ *   2. the CRBM free energy F(x') of Eq. (free-energy_CRBM);
+ *   3. the target: the Ising energy E(x') of Sec. III (integer, exact), or the
+ *      Kitaev gauge-field weight S(x') = -beta F(x') of Sec. IV from the FP64
+ *      singular values of the Majorana hopping block;
+ *   4. the Metropolis-Hastings test of Eq. (acceptance) with one replica being
+ *      the CRBM: log r = log P(x') - log P(x) + F(x') - F(x); accept iff
+ *      log u < log r;
+ *   5. observables of the state after the sweep (after burn-in).
+ *
+ * Conventions common to every entry point
+ *   - Pointers marked "device" are HIP device pointers owned by the caller;
+ *     the library allocates no device memory.  Pointers marked "host" are
+ *     ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All calls are asynchronous with respect to the host and ordered on
+ *     that stream, unless stated otherwise.
+ *   - Spin states are int8 +-1 with layout [chain][C][L][L], row-major.
+ *     The CRBM works on v = (s+1)/2 (App. A).  Ising uses C = 1.  Kitaev uses
+ *     C = 3 (bond variables u_x, u_y, u_z of unit cell (i,j), see below) or
+ *     C = 1 (only the z-bond field eta, u_x = u_y = +1, as in Sec. IV).
+ *   - CRBM filters are float32 W[K][C][Lw][Lw]; the "wrap around convolution"
+ *     is a cross-correlation anchored at the filter's top-left element:
+ *       a[k][i][j] = hbias[k] + sum_{c,a,b} W[k][c][a][b] v[c][(i+a)%L][(j+b)%L]
+ *     and the hidden->visible pass is its exact adjoint:
+ *       b[c][x][y] = vbias[c] + sum_{k,a,b} W[k][c][a][b] h[k][(x-a)%L][(y-b)%L].
+ *   - Random numbers: Philox4x32-10 with key = seed and counter
+ *     (unit>>2, sweep, chain, tag), word unit&3; tag = stream | substep<<8,
+ *     streams INIT=0, HID=1, VIS=2, MH=3.  Hidden unit index
+ *     (k*L+i)*L+j, visible unit index (c*L+i)*L+j.  A unit is on iff
+ *     (x+0.5)/2^32 < sigmoid(pre-activation); the MH uniform is the 53-bit
+ *     number from words 0 and 1 of unit group 0.  The initial state takes
+ *     s = +1 iff the top bit of its INIT word is set.
+ *   - Every entry point validates its arguments on the host and returns a
+ *     negative crbm_status on error without launching anything; the message
+ *     is available from crbm_last_error().  Faults of launched kernels
+ *     surface as CRBM_EHIP at the next call that synchronises.
+ *   - Kitaev lattice: unit cell (i,j) holds a black site b and a white site w;
+ *     the z bond joins b(i,j)-w(i,j), the x bond b(i,j)-w(i,(j+1)%L), the y
+ *     bond b(i,j)-w((i+1)%L,j).  M[b,w] = 2 J_alpha u_alpha (N x N, N = L^2).
+ */
+#ifndef CRBM_H
+#define CRBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef CRBM_API
+#define CRBM_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRBM_OK = 0,
+    CRBM_EINVAL = -1,      /* invalid argument (shape, size, null pointer, range) */
+    CRBM_EBUDGET = -2,     /* workspace too small */
+    CRBM_EHIP = -3,        /* a HIP runtime call failed */
+    CRBM_EUNSUPPORTED = -4 /* valid but not supported by this build (e.g. LDS too small) */
+} crbm_status;
+
+typedef enum { CRBM_ISING = 0, CRBM_KITAEV = 1 } crbm_target;
+
+/* CRBM parameters theta = (W, hbias, vbias); all device, float32.
+ * K in [1, 64], C in {1, 3}, Lw in [1, 8] and Lw <= L. */
+typedef struct {
+    int32_t K, C, Lw;
+    const float* W;     /* device [K][C][Lw][Lw] */
+    const float* hbias; /* device [K] */
+    const float* vbias; /* device [C] */
+} crbm_params;
+
+/* One job: n_chains chains on an L x L lattice.
+ * T[g] > 0 is chain g's temperature.  Chain g uses the Philox chain index
+ * chain_offset + g, so a chain's trajectory depends only on (seed, its index,
+ * sweep number), never on how jobs are batched. */
+typedef struct {
+    int32_t target;        /* crbm_target */
+    int32_t L;             /* lattice side, 1 <= L <= 256 */
+    int32_t n_chains;      /* >= 1 */
+    int32_t gibbs_k;       /* Gibbs steps per proposal, >= 1 */
+    int32_t burnin_sweeps; /* sweeps with index < burnin are not measured */
+    int32_t init_state;    /* 1: crbm_init fills `state` from the INIT stream */
+    uint32_t chain_offset; /* Philox chain index of chain 0 */
+    int32_t reserved;
+    uint64_t seed;         /* Philox key */
+    double J[3];           /* Ising: J[0] is J. Kitaev: J_x, J_y, J_z */
+    const double* T;       /* device [n_chains] temperatures */
+    int8_t* state;         /* device [n_chains][C][L][L], +-1, read and written */
+    void* workspace;       /* device, >= crbm_workspace_size() bytes */
+    size_t workspace_bytes;
+} crbm_batch_desc;
+
+/* Per-chain record, kept in the workspace; read with crbm_read_stats.
+ * Sums cover the measured sweeps (sweep index >= burnin_sweeps) and use the
+ * state after each sweep. Ising sums are exact integers in units of J. */
+typedef struct {
+    int64_t sweeps;       /* sweeps done */
+    int64_t n_acc;        /* accepted proposals (all sweeps) */
+    int64_t n_meas;       /* measured sweeps */
+    int64_t n_recheck;    /* decisions re-evaluated in FP64 (diagnostic) */
+    int64_t sumE, sumE2;  /* Ising: sum E/J, sum (E/J)^2 */
+    int64_t sumM, sumAbsM, sumM2;
+    int64_t E;            /* Ising E/J of the current state */
+    double F;             /* CRBM free energy of the current state */
+    double S;             /* Kitaev -beta F_gauge of the current state */
+    double Ef;            /* Kitaev fermion energy -sum eps/2 tanh(beta eps/2) */
+    double Cf;            /* Kitaev sum (beta eps/2)^2 / cosh^2(beta eps/2) */
+    double kE, kE2, kCf;  /* Kitaev sums of Ef, Ef^2, Cf */
+    double reserved[3];
+} crbm_chain_stats;
+
+typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
+
+/* Bytes of device workspace a job needs (per-chain records plus internal
+ * buffers).  Returns 0 for invalid arguments. Host only, no device work. */
+CRBM_API size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* desc);
+
+/* Create a job handle: copies `params`/`desc` (the pointed-to device buffers
+ * must stay valid until crbm_destroy), optionally fills the initial state,
+ * computes F and the target of every chain's state and zeroes the sums.
+ * Sweep numbering starts at 0. Asynchronous on `stream`. */
+CRBM_API crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batch_desc* desc, void* stream);
+
+/* Advance every chain of the job by n_sweeps >= 0 sweeps (steps 1-5 above).
+ * Asynchronous on the job's stream; updates `state` and the workspace. */
+CRBM_API crbm_status crbm_propose_accept(crbm_ctx* ctx, int32_t n_sweeps);
+
+/* Advance several jobs by n_sweeps each in shared launches (continuous
+ * batching). All jobs must use the same stream. */
+CRBM_API crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps);
+
+/* Copy the per-chain records, n_chains x crbm_chain_stats, to `out`
+ * (device memory if on_device != 0, else host memory; the host copy
+ * synchronises the stream). */
+CRBM_API crbm_status crbm_read_stats(crbm_ctx* ctx, crbm_chain_stats* out, int32_t on_device);
+
+/* Sweeps done so far by the job. Host only. */
+CRBM_API int64_t crbm_sweeps_done(const crbm_ctx* ctx);
+
+/* Release the handle (host memory only; caller-owned buffers untouched). */
+CRBM_API crbm_status crbm_destroy(crbm_ctx* ctx);
+
+/* CRBM free energy, Eq. (free-energy_CRBM), of B states x[B][C][L][L] (+-1,
+ * device) -> F_out[B] (device, FP64).  Terms and sums in FP64. */
+CRBM_API crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x, int32_t B, int32_t L,
+                             double* F_out, void* stream);
+
+/* Target of B states x[B][C][L][L] (device).
+ * CRBM_ISING (C must be 1): E_out[B] = E/J = -sum_<ij> s_i s_j (device int32,
+ *   exact); S_out ignored (may be NULL).
+ * CRBM_KITAEV (C = 1 or 3): S_out[B] = sum_lambda log 2cosh(eps_lambda/(2 T[b]))
+ *   (device FP64) over the N = L^2 singular values of M; T is device [B];
+ *   E_out ignored. L <= 12 for Kitaev. */
+CRBM_API crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L,
+                          const double J[3] /* host */, const double* T, int32_t* E_out,
+                          double* S_out, void* stream);
+
+/* Vector-Jacobian product of F (the backward of the loss of Eq. (loss)):
+ * dW = sum_b gF[b] dF(x_b)/dW, likewise dhbias, dvbias, with
+ *   dF/dW[k][c][a][b'] = -sum_ij sigmoid(a[k][i][j]) v[c][(i+a)%L][(j+b')%L]
+ *   dF/dhbias[k]       = -sum_ij sigmoid(a[k][i][j])
+ *   dF/dvbias[c]       = -sum_ij v[c][i][j].
+ * x[B][C][L][L] +-1 device; gF[B] float32 device; outputs float32 device,
+ * overwritten.  Per-sample sums in FP32 terms / FP64 accumulation, the sum
+ * over samples in FP64 in a fixed order (deterministic). `workspace` is a
+ * device buffer of crbm_grad_workspace_size(params, B) bytes. */
+CRBM_API size_t crbm_grad_workspace_size(const crbm_params* params, int32_t B);
+CRBM_API crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int32_t L, const float* gF,
+                      float* dW, float* dhbias, float* dvbias, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+CRBM_API const char* crbm_last_error(void);
+
+/* Version string of the library. */
+CRBM_API const char* crbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRBM_H */

@@ -1,0 +1,186 @@
+"""Python interface of the CRBM sampler on MI355X.
+
+torch provides device memory and the stream; every step of the sampler runs in
+the HIP kernels of libcrbm.so (see include/crbm.h for the operations and
+their paper references).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+ISING, KITAEV = C.CRBM_ISING, C.CRBM_KITAEV
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev(device=None):
+    return torch.device(device if device is not None else "cuda")
+
+
+class CRBMParams:
+    """Filters W[K][C][Lw][Lw], hbias[K], vbias[C] as float32 device tensors."""
+
+    def __init__(self, W, hbias, vbias, device=None):
+        dev = _dev(device)
+        self.W = torch.as_tensor(np.asarray(W, np.float32) if not torch.is_tensor(W) else W,
+                                 dtype=torch.float32, device=dev).contiguous()
+        self.hbias = torch.as_tensor(np.asarray(hbias, np.float32) if not torch.is_tensor(hbias) else hbias,
+                                     dtype=torch.float32, device=dev).contiguous().reshape(-1)
+        self.vbias = torch.as_tensor(np.asarray(vbias, np.float32) if not torch.is_tensor(vbias) else vbias,
+                                     dtype=torch.float32, device=dev).contiguous().reshape(-1)
+        assert self.W.dim() == 4 and self.W.shape[2] == self.W.shape[3]
+        self.K, self.C, self.Lw = int(self.W.shape[0]), int(self.W.shape[1]), int(self.W.shape[2])
+        assert self.hbias.numel() == self.K and self.vbias.numel() == self.C
+
+    @classmethod
+    def from_filters(cls, f, device=None):
+        return cls(f.W, f.hbias, f.vbias, device)
+
+    def struct(self) -> C.crbm_params:
+        return C.crbm_params(self.K, self.C, self.Lw, self.W.data_ptr(), self.hbias.data_ptr(),
+                             self.vbias.data_ptr())
+
+
+class Job:
+    """n independent chains of the CRBM-proposal + MH sampler, resident on the GPU."""
+
+    def __init__(self, params: CRBMParams, target: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
+                 burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, chain_offset: int = 0, stream=None):
+        dev = params.W.device
+        self.params = params
+        self.target = int(target)
+        self.L = int(L)
+        self.T = torch.as_tensor(np.asarray(T, np.float64).reshape(-1), device=dev).contiguous()
+        n = int(self.T.numel())
+        self.n_chains = n
+        shape = (n, params.C, self.L, self.L)
+        if state is None:
+            self.state = torch.empty(shape, dtype=torch.int8, device=dev)
+            init = 1
+        else:
+            st = state if torch.is_tensor(state) else torch.from_numpy(np.ascontiguousarray(state, np.int8))
+            self.state = st.to(device=dev, dtype=torch.int8).contiguous().clone()
+            assert tuple(self.state.shape) == shape
+            init = 0
+        self._p = params.struct()
+        self._stream = stream
+        self._desc = C.crbm_batch_desc(self.target, self.L, n, int(gibbs_k), int(burnin), init,
+                                       int(chain_offset), 0, int(seed), (C.ct.c_double * 3)(*J),
+                                       self.T.data_ptr(), self.state.data_ptr(), 0, 0)
+        ws = C.crbm_workspace_size(self._p, self._desc)
+        if ws == 0:
+            # let crbm_init produce the precise error message
+            ws = 256
+        self.workspace = torch.zeros(ws + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._desc.workspace = aligned
+        self._desc.workspace_bytes = ws + 256 - (aligned - base)
+        self.ctx = C.crbm_init(self._p, self._desc, _stream_ptr(stream))
+
+    def run(self, n_sweeps: int):
+        C.crbm_propose_accept(self.ctx, int(n_sweeps))
+        return self
+
+    @property
+    def sweeps(self) -> int:
+        return C.crbm_sweeps_done(self.ctx)
+
+    def stats(self) -> np.ndarray:
+        out = np.zeros(self.n_chains, C.STATS_DTYPE)
+        C.crbm_read_stats(self.ctx, out.ctypes.data, False)
+        return out
+
+    def stats_device(self) -> torch.Tensor:
+        out = torch.empty(self.n_chains * C.STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.state.device)
+        C.crbm_read_stats(self.ctx, out.data_ptr(), True)
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            C.crbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_many(jobs, n_sweeps: int):
+    """Advance several jobs (same stream) by n_sweeps in shared launches."""
+    C.crbm_propose_accept_many([j.ctx for j in jobs], int(n_sweeps))
+
+
+def free_energy(params: CRBMParams, x: torch.Tensor, stream=None) -> torch.Tensor:
+    x = x.to(device=params.W.device, dtype=torch.int8).contiguous()
+    B, L = int(x.shape[0]), int(x.shape[-1])
+    F = torch.empty(B, dtype=torch.float64, device=x.device)
+    C.crbm_free_energy(params.struct(), x.data_ptr(), B, L, F.data_ptr(), _stream_ptr(stream))
+    return F
+
+
+def ising_energy(x: torch.Tensor, stream=None) -> torch.Tensor:
+    x = x.to(dtype=torch.int8).contiguous()
+    B, L = int(x.shape[0]), int(x.shape[-1])
+    E = torch.empty(B, dtype=torch.int32, device=x.device)
+    C.target_energy(ISING, x.data_ptr(), B, 1, L, (1.0, 1.0, 1.0), None, E.data_ptr(), None,
+                    _stream_ptr(stream))
+    return E
+
+
+def kitaev_weight(u: torch.Tensor, T, J=(1.0, 1.0, 1.0), stream=None) -> torch.Tensor:
+    u = u.to(dtype=torch.int8).contiguous()
+    B, Cc, L = int(u.shape[0]), int(u.shape[1]), int(u.shape[-1])
+    Tt = torch.as_tensor(np.asarray(T, np.float64).reshape(-1), device=u.device).contiguous()
+    assert Tt.numel() == B
+    S = torch.empty(B, dtype=torch.float64, device=u.device)
+    C.target_energy(KITAEV, u.data_ptr(), B, Cc, L, J, Tt.data_ptr(), None, S.data_ptr(), _stream_ptr(stream))
+    return S
+
+
+def grad(params: CRBMParams, x: torch.Tensor, gF: torch.Tensor, stream=None):
+    """sum_b gF[b] dF(x_b)/d(W, hbias, vbias) as float32 device tensors."""
+    x = x.to(device=params.W.device, dtype=torch.int8).contiguous()
+    B, L = int(x.shape[0]), int(x.shape[-1])
+    g = gF.to(device=x.device, dtype=torch.float32).contiguous().reshape(B)
+    p = params.struct()
+    ws_bytes = C.crbm_grad_workspace_size(p, B)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
+    dW = torch.empty_like(params.W)
+    dhb = torch.empty_like(params.hbias)
+    dvb = torch.empty_like(params.vbias)
+    C.crbm_grad(p, x.data_ptr(), B, L, g.data_ptr(), dW.data_ptr(), dhb.data_ptr(), dvb.data_ptr(),
+                ws.data_ptr(), ws_bytes, _stream_ptr(stream))
+    return dW, dhb, dvb
+
+
+class CRBMFreeEnergy(torch.autograd.Function):
+    """F(x; W, hbias, vbias) with the hand-written backward kernel.
+
+    forward(x, W, hbias, vbias) -> F[B] (float64); backward returns
+    (None, dW, dhbias, dvbias) with d = sum_b grad_out[b] dF_b/dtheta."""
+
+    @staticmethod
+    def forward(ctx, x, W, hbias, vbias):
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device)
+        ctx.save_for_backward(x, W, hbias, vbias)
+        return free_energy(p, x)
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, W, hbias, vbias = ctx.saved_tensors
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device)
+        dW, dhb, dvb = grad(p, x, gout.to(torch.float32))
+        return None, dW, dhb, dvb
+
+
+def crbm_free_energy_fn(x, W, hbias, vbias):
+    return CRBMFreeEnergy.apply(x, W, hbias, vbias)

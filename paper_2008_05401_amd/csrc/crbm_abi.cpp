@@ -1,0 +1,352 @@
+// crbm_abi.cpp -- host side of the C ABI declared in include/crbm.h:
+// argument validation, workspace layout, kernel selection and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/crbm.h"
+#include "ops.h"
+#include "sweep_common.h"
+#include "sweep_ising.h"
+
+using namespace crbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+crbm_status fail(crbm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+crbm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(CRBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kJobBytes = 256;
+static_assert(sizeof(JobDev) <= kJobBytes, "job descriptor fits its slot");
+static_assert(sizeof(crbm_chain_stats) == sizeof(ChainRec), "record layout");
+
+crbm_status check_params(const crbm_params* p)
+{
+    if (!p) return fail(CRBM_EINVAL, "params is NULL");
+    if (p->K < 1 || p->K > 64) return fail(CRBM_EINVAL, "K=%d outside [1,64]", p->K);
+    if (p->C != 1 && p->C != 3) return fail(CRBM_EINVAL, "C=%d must be 1 or 3", p->C);
+    if (p->Lw < 1 || p->Lw > 8) return fail(CRBM_EINVAL, "Lw=%d outside [1,8]", p->Lw);
+    if (!p->W || !p->hbias || !p->vbias) return fail(CRBM_EINVAL, "W, hbias and vbias must be device pointers");
+    return CRBM_OK;
+}
+
+enum Kernel { K_GENERIC = 0, K_ISING_FAST = 1 };
+
+struct Plan {
+    int kernel;
+    int nt;
+    size_t lds;
+};
+
+crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
+{
+    crbm_status st = check_params(p);
+    if (st != CRBM_OK) return st;
+    if (!d) return fail(CRBM_EINVAL, "desc is NULL");
+    if (d->target != CRBM_ISING && d->target != CRBM_KITAEV) return fail(CRBM_EINVAL, "unknown target %d", d->target);
+    if (d->L < 1 || d->L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", d->L);
+    if (p->Lw > d->L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", p->Lw, d->L);
+    if (d->n_chains < 1) return fail(CRBM_EINVAL, "n_chains=%d must be >= 1", d->n_chains);
+    if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
+    if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
+    if (d->target == CRBM_ISING && p->C != 1) return fail(CRBM_EINVAL, "Ising needs C=1 (got %d)", p->C);
+    if (d->target == CRBM_KITAEV && d->L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", d->L);
+    Plan pl{};
+    if (d->target == CRBM_ISING && ising_fast_supported(p->K, p->Lw, d->L)) {
+        pl.kernel = K_ISING_FAST;
+        pl.nt = ising_fast_threads(d->L);
+        pl.lds = ising_fast_lds_bytes(p->K, p->Lw, d->L);
+    } else {
+        pl.kernel = K_GENERIC;
+        pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
+        pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target);
+    }
+    if (pl.lds > kLdsLimit)
+        return fail(CRBM_EUNSUPPORTED, "job needs %zu bytes of LDS per chain (limit %zu)", pl.lds, kLdsLimit);
+    *out = pl;
+    return CRBM_OK;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t workspace_bytes_for(int n_chains) { return round_up(kJobBytes + (size_t)n_chains * sizeof(ChainRec), 256); }
+
+}  // namespace
+
+struct crbm_ctx {
+    crbm_params params;
+    crbm_batch_desc desc;
+    hipStream_t stream;
+    JobDev job;
+    JobDev* job_dev;
+    ChainRec* rec;
+    Plan plan;
+    int64_t sweeps;
+};
+
+namespace {
+
+crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
+{
+    // group by kernel variant (and thread count / LDS) and chunk by MAX_JOBS_PER_LAUNCH
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const Plan& pa = ctxs[a]->plan;
+        const Plan& pb = ctxs[b]->plan;
+        if (pa.kernel != pb.kernel) return pa.kernel < pb.kernel;
+        if (pa.nt != pb.nt) return pa.nt < pb.nt;
+        if (pa.kernel == K_ISING_FAST && ctxs[a]->params.K != ctxs[b]->params.K) return ctxs[a]->params.K < ctxs[b]->params.K;
+        if (pa.kernel == K_ISING_FAST && ctxs[a]->params.Lw != ctxs[b]->params.Lw)
+            return ctxs[a]->params.Lw < ctxs[b]->params.Lw;
+        return false;
+    });
+    hipStream_t s = ctxs[0]->stream;
+    size_t i = 0;
+    while (i < order.size()) {
+        const crbm_ctx* c0 = ctxs[order[i]];
+        SweepLaunch P;
+        memset(&P, 0, sizeof P);
+        P.n_sweeps = n_sweeps;
+        P.mode = mode;
+        size_t lds = 0;
+        int blocks = 0;
+        int nj = 0;
+        while (i < order.size() && nj < MAX_JOBS_PER_LAUNCH) {
+            const crbm_ctx* c = ctxs[order[i]];
+            if (c->plan.kernel != c0->plan.kernel || c->plan.nt != c0->plan.nt) break;
+            if (c0->plan.kernel == K_ISING_FAST && (c->params.K != c0->params.K || c->params.Lw != c0->params.Lw)) break;
+            P.jobs[nj] = c->job_dev;
+            P.block_begin[nj] = blocks;
+            blocks += c->desc.n_chains;
+            lds = std::max(lds, c->plan.lds);
+            ++nj;
+            ++i;
+        }
+        P.block_begin[nj] = blocks;
+        P.n_jobs = nj;
+        hipError_t e;
+        if (c0->plan.kernel == K_ISING_FAST)
+            e = launch_ising_fast(P, c0->params.K, c0->params.Lw, blocks, lds, c0->plan.nt, s);
+        else
+            e = launch_generic(P, blocks, lds, c0->plan.nt, s);
+        if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    }
+    return CRBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* desc)
+{
+    Plan pl;
+    if (plan_job(params, desc, &pl) != CRBM_OK) return 0;
+    return workspace_bytes_for(desc->n_chains);
+}
+
+crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batch_desc* desc, void* stream)
+{
+    if (!out) return fail(CRBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Plan pl;
+    crbm_status st = plan_job(params, desc, &pl);
+    if (st != CRBM_OK) return st;
+    if (!desc->T || !desc->state || !desc->workspace) return fail(CRBM_EINVAL, "T, state and workspace must be device pointers");
+    const size_t need = workspace_bytes_for(desc->n_chains);
+    if (desc->workspace_bytes < need)
+        return fail(CRBM_EBUDGET, "workspace of %zu bytes, %zu needed", desc->workspace_bytes, need);
+    if (((uintptr_t)desc->workspace & 255) != 0) return fail(CRBM_EINVAL, "workspace must be 256-byte aligned");
+    crbm_ctx* c = new (std::nothrow) crbm_ctx;
+    if (!c) return fail(CRBM_EINVAL, "out of host memory");
+    c->params = *params;
+    c->desc = *desc;
+    c->stream = (hipStream_t)stream;
+    c->plan = pl;
+    c->sweeps = 0;
+    c->job_dev = (JobDev*)desc->workspace;
+    c->rec = (ChainRec*)((char*)desc->workspace + kJobBytes);
+    JobDev& j = c->job;
+    memset(&j, 0, sizeof j);
+    j.W = params->W;
+    j.hb = params->hbias;
+    j.vb = params->vbias;
+    j.T = desc->T;
+    j.state = desc->state;
+    j.rec = c->rec;
+    j.J0 = desc->J[0];
+    j.J1 = desc->J[1];
+    j.J2 = desc->J[2];
+    j.seed = desc->seed;
+    j.K = params->K;
+    j.C = params->C;
+    j.LW = params->Lw;
+    j.target = desc->target;
+    j.L = desc->L;
+    j.n_chains = desc->n_chains;
+    j.gibbs_k = desc->gibbs_k;
+    j.burnin = desc->burnin_sweeps;
+    j.chain_offset = desc->chain_offset;
+    j.init_state = desc->init_state;
+    hipError_t e = hipMemcpyAsync(c->job_dev, &c->job, sizeof(JobDev), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipMemcpyAsync(job)");
+    }
+    crbm_ctx* one[1] = {c};
+    st = launch_jobs(one, 1, 0, MODE_INIT);
+    if (st != CRBM_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return CRBM_OK;
+}
+
+crbm_status crbm_propose_accept(crbm_ctx* ctx, int32_t n_sweeps)
+{
+    if (!ctx) return fail(CRBM_EINVAL, "ctx is NULL");
+    if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps=%d must be >= 0", n_sweeps);
+    if (n_sweeps == 0) return CRBM_OK;
+    crbm_ctx* one[1] = {ctx};
+    crbm_status st = launch_jobs(one, 1, n_sweeps, MODE_SWEEP);
+    if (st == CRBM_OK) ctx->sweeps += n_sweeps;
+    return st;
+}
+
+crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps)
+{
+    if (!ctxs || n_ctx < 0) return fail(CRBM_EINVAL, "invalid job list");
+    if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps=%d must be >= 0", n_sweeps);
+    if (n_ctx == 0 || n_sweeps == 0) return CRBM_OK;
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return fail(CRBM_EINVAL, "job %d is NULL", i);
+        if (ctxs[i]->stream != ctxs[0]->stream) return fail(CRBM_EINVAL, "jobs must share one stream");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(CRBM_EINVAL, "job %d listed twice", i);
+    }
+    crbm_status st = launch_jobs(ctxs, n_ctx, n_sweeps, MODE_SWEEP);
+    if (st == CRBM_OK)
+        for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps += n_sweeps;
+    return st;
+}
+
+crbm_status crbm_read_stats(crbm_ctx* ctx, crbm_chain_stats* out, int32_t on_device)
+{
+    if (!ctx || !out) return fail(CRBM_EINVAL, "ctx and out must not be NULL");
+    const size_t bytes = sizeof(ChainRec) * (size_t)ctx->desc.n_chains;
+    hipError_t e;
+    if (on_device) {
+        e = hipMemcpyAsync(out, ctx->rec, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+    } else {
+        e = hipMemcpyAsync(out, ctx->rec, bytes, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "crbm_read_stats");
+    return CRBM_OK;
+}
+
+int64_t crbm_sweeps_done(const crbm_ctx* ctx) { return ctx ? ctx->sweeps : -1; }
+
+crbm_status crbm_destroy(crbm_ctx* ctx)
+{
+    delete ctx;
+    return CRBM_OK;
+}
+
+crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x, int32_t B, int32_t L, double* F_out,
+                             void* stream)
+{
+    crbm_status st = check_params(params);
+    if (st != CRBM_OK) return st;
+    if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
+    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
+    if (params->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", params->Lw, L);
+    if (B == 0) return CRBM_OK;
+    if (!x || !F_out) return fail(CRBM_EINVAL, "x and F_out must be device pointers");
+    if (free_energy_lds(params->K, params->C, params->Lw, L) > kLdsLimit)
+        return fail(CRBM_EUNSUPPORTED, "free energy needs too much LDS for L=%d", L);
+    hipError_t e = launch_free_energy(params->W, params->hbias, params->vbias, params->K, params->C, params->Lw, x, B, L,
+                                      F_out, (hipStream_t)stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_free_energy launch");
+}
+
+crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L, const double J[3],
+                          const double* T, int32_t* E_out, double* S_out, void* stream)
+{
+    if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
+    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
+    if (target == CRBM_ISING) {
+        if (C != 1) return fail(CRBM_EINVAL, "Ising needs C=1 (got %d)", C);
+        if (B == 0) return CRBM_OK;
+        if (!x || !E_out) return fail(CRBM_EINVAL, "x and E_out must be device pointers");
+        hipError_t e = launch_ising_energy(x, B, L, E_out, (hipStream_t)stream);
+        return e == hipSuccess ? CRBM_OK : hip_fail(e, "target_energy launch");
+    }
+    if (target == CRBM_KITAEV) {
+        if (C != 1 && C != 3) return fail(CRBM_EINVAL, "Kitaev needs C=1 or 3 (got %d)", C);
+        if (L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", L);
+        if (!J) return fail(CRBM_EINVAL, "J must point to 3 host doubles");
+        if (B == 0) return CRBM_OK;
+        if (!x || !S_out || !T) return fail(CRBM_EINVAL, "x, T and S_out must be device pointers");
+        hipError_t e = launch_kitaev_weight(x, B, C, L, J[0], J[1], J[2], T, S_out, (hipStream_t)stream);
+        return e == hipSuccess ? CRBM_OK : hip_fail(e, "target_energy launch");
+    }
+    return fail(CRBM_EINVAL, "unknown target %d", target);
+}
+
+size_t crbm_grad_workspace_size(const crbm_params* params, int32_t B)
+{
+    if (check_params(params) != CRBM_OK || B < 0) return 0;
+    const size_t P = (size_t)params->K * params->C * params->Lw * params->Lw + params->K + params->C;
+    return round_up(std::max<size_t>(1, (size_t)B) * P * sizeof(double), 256);
+}
+
+crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int32_t L, const float* gF, float* dW,
+                      float* dhbias, float* dvbias, void* workspace, size_t workspace_bytes, void* stream)
+{
+    crbm_status st = check_params(params);
+    if (st != CRBM_OK) return st;
+    if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
+    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
+    if (params->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", params->Lw, L);
+    if (!dW || !dhbias || !dvbias) return fail(CRBM_EINVAL, "gradient outputs must be device pointers");
+    if (B > 0 && (!x || !gF)) return fail(CRBM_EINVAL, "x and gF must be device pointers");
+    const size_t need = crbm_grad_workspace_size(params, B);
+    if (!workspace || workspace_bytes < need)
+        return fail(CRBM_EBUDGET, "grad workspace of %zu bytes, %zu needed", workspace_bytes, need);
+    if (grad_lds(params->K, params->C, params->Lw, L) > kLdsLimit)
+        return fail(CRBM_EUNSUPPORTED, "gradient needs too much LDS for L=%d", L);
+    hipError_t e = launch_grad(params->W, params->hbias, params->K, params->C, params->Lw, x, B, L, gF,
+                               (double*)workspace, dW, dhbias, dvbias, (hipStream_t)stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_grad launch");
+}
+
+const char* crbm_last_error(void) { return g_err.c_str(); }
+
+const char* crbm_version(void) { return "crbm-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// device_common.h -- device helpers shared by the gfx950 kernels of the CRBM
+// sampler: Philox4x32-10, uniforms, guarded Bernoulli decisions, wavefront
+// and workgroup reductions, per-chain record layout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crbm {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32
+// multiply-xor S-box; the two key words advance by the Weyl constants between
+// rounds.  Counter (unit>>2, sweep, chain, tag), key = 64-bit seed.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+enum : uint32_t { STREAM_INIT = 0, STREAM_HID = 1, STREAM_VIS = 2, STREAM_MH = 3 };
+
+__device__ __forceinline__ uint32_t word_of(const u32x4& r, int w)
+{
+    return w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
+}
+
+// 53-bit MH uniform of (chain, sweep): words 0,1 of unit group 0
+__device__ __forceinline__ double mh_uniform(uint64_t seed, uint32_t t, uint32_t g)
+{
+    const u32x4 r = philox10(0u, t, g, STREAM_MH, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t x = ((uint64_t)r.x << 32) | (uint64_t)r.y;
+    return ((double)(x >> 11) + 0.5) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Bernoulli decision h = [u < sigmoid(a)], u = (x + 0.5) 2^-32.
+// Fast path in float32: with e = exp(-a), u < sigmoid(a)  <=>  u (1 + e) - 1 < 0.
+// `dA` bounds |a_f32 - a_exact| (float32 summation of the pre-activation).
+// The remaining error of the test value is below
+//   dA + |a| 2^-22 + 2^-19
+// (argument rounding of exp2, exp2 result, product, float conversion of u),
+// so outside that band the float32 sign is the exact one; inside it the
+// caller re-evaluates in FP64 (`near` is set).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool bernoulli_fast(float a, uint32_t x, float dA, bool& near)
+{
+    const float u = ((float)x + 0.5f) * 0x1p-32f;
+    const float e = __builtin_amdgcn_exp2f(-a * 1.44269504088896341f);
+    const float tt = fmaf(u, e, u) - 1.0f;
+    const float bound = dA + fabsf(a) * 0x1p-22f + 0x1p-19f;
+    near = fabsf(tt) <= bound;
+    return tt < 0.0f;
+}
+
+__device__ __forceinline__ bool bernoulli_exact(double a, uint32_t x)
+{
+    const double u = ((double)x + 0.5) * 0x1p-32;
+    const double p = 1.0 / (1.0 + exp(-a));
+    return u < p;
+}
+
+__device__ __forceinline__ double softplus_d(double x)
+{
+    return (x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x)));
+}
+
+__device__ __forceinline__ double log2cosh_d(double x)
+{
+    const double ax = fabs(x);
+    return ax + log1p(exp(-2.0 * ax));
+}
+
+// gamma_n = n u / (1 - n u), u = 2^-24: bound factor of n-term float32 sums
+__host__ __device__ inline float gamma_f32(int n)
+{
+    const double nu = (double)n * 0x1p-24;
+    return (float)(nu / (1.0 - nu));
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Workgroup sum; `red` is LDS scratch of >= nwaves entries.  Every thread
+// receives the total.  Contains two barriers.
+template <typename Tv>
+__device__ __forceinline__ Tv block_sum(Tv v, Tv* red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    Tv s = 0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Per-chain record (same layout as crbm_chain_stats of the C ABI)
+// ---------------------------------------------------------------------------
+struct ChainRec {
+    long long sweeps, n_acc, n_meas, n_recheck;
+    long long sumE, sumE2, sumM, sumAbsM, sumM2;
+    long long E;
+    double F, S, Ef, Cf;
+    double kE, kE2, kCf;
+    double reserved[3];
+};
+static_assert(sizeof(ChainRec) == 160, "record layout");
+
+}  // namespace crbm

@@ -1,0 +1,214 @@
+// ops.hip -- stand-alone kernels of the C ABI: batched CRBM free energy,
+// target energies (Ising E, Kitaev S) and the backward of F.
+#include "device_common.h"
+#include "kitaev_eig.h"
+#include "ops.h"
+
+namespace crbm {
+
+// ---------------------------------------------------------------------------
+// F(x_b) of Eq. (free-energy_CRBM), FP64 terms and sums; one workgroup per state.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void free_energy_kernel(const float* __restrict__ W, const float* __restrict__ hb,
+                                                          const float* __restrict__ vb, int K, int C, int LW,
+                                                          const int8_t* __restrict__ x, int L, double* __restrict__ F)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int LL = L * L, nW = K * C * LW * LW;
+    double* red = (double*)smem;
+    double* Wd = red + 64;
+    double* hbd = Wd + nW;
+    uint8_t* v = (uint8_t*)(hbd + K);
+    const int8_t* xs = x + (size_t)blockIdx.x * C * LL;
+    for (int q = threadIdx.x; q < nW; q += blockDim.x) Wd[q] = (double)W[q];
+    for (int q = threadIdx.x; q < K; q += blockDim.x) hbd[q] = (double)hb[q];
+    for (int q = threadIdx.x; q < C * LL; q += blockDim.x) v[q] = xs[q] > 0;
+    __syncthreads();
+    double fl = 0.0;
+    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
+        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
+        double acc = hbd[k];
+        for (int c = 0; c < C; ++c)
+            for (int a = 0; a < LW; ++a) {
+                int ia = i + a;
+                if (ia >= L) ia -= L;
+                const uint8_t* row = v + (c * L + ia) * L;
+                const double* wr = Wd + ((k * C + c) * LW + a) * LW;
+                for (int b = 0; b < LW; ++b) {
+                    int jb = j + b;
+                    if (jb >= L) jb -= L;
+                    acc += row[jb] ? wr[b] : 0.0;
+                }
+            }
+        fl -= softplus_d(acc);
+    }
+    for (int q = threadIdx.x; q < C * LL; q += blockDim.x) fl -= (double)vb[q / LL] * (double)v[q];
+    const double tot = block_sum(fl, red);
+    if (threadIdx.x == 0) F[blockIdx.x] = tot;
+}
+
+size_t free_energy_lds(int K, int C, int LW, int L)
+{
+    return 64 * 8 + (size_t)(K * C * LW * LW + K) * 8 + (size_t)C * L * L + 16;
+}
+
+hipError_t launch_free_energy(const float* W, const float* hb, const float* vb, int K, int C, int LW, const int8_t* x,
+                              int B, int L, double* F, hipStream_t s)
+{
+    hipLaunchKernelGGL(free_energy_kernel, dim3(B), dim3(256), free_energy_lds(K, C, LW, L), s, W, hb, vb, K, C, LW, x,
+                       L, F);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ising E/J = -sum_<ij> s_i s_j, exact int32; one workgroup per state.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ising_energy_kernel(const int8_t* __restrict__ x, int L, int32_t* __restrict__ E)
+{
+    __shared__ int red[16];
+    const int LL = L * L;
+    const int8_t* s = x + (size_t)blockIdx.x * LL;
+    int el = 0;
+    for (int q = threadIdx.x; q < LL; q += blockDim.x) {
+        const int i = q / L, j = q - i * L;
+        el -= (int)s[q] * ((int)s[(i + 1 == L ? 0 : i + 1) * L + j] + (int)s[i * L + (j + 1 == L ? 0 : j + 1)]);
+    }
+    const int tot = block_sum(el, red);
+    if (threadIdx.x == 0) E[blockIdx.x] = tot;
+}
+
+hipError_t launch_ising_energy(const int8_t* x, int B, int L, int32_t* E, hipStream_t s)
+{
+    hipLaunchKernelGGL(ising_energy_kernel, dim3(B), dim3(256), 0, s, x, L, E);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Kitaev S = sum log 2cosh(eps / 2T), FP64; one workgroup per configuration.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, double Jx,
+                                                            double Jy, double Jz, const double* __restrict__ T,
+                                                            double* __restrict__ S)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = L * L;
+    double* red = (double*)smem;
+    double* A = red + 64;
+    uint8_t* v = (uint8_t*)(A + N * (N + 1) / 2 + 4 * N);
+    const int8_t* xs = x + (size_t)blockIdx.x * C * N;
+    for (int q = threadIdx.x; q < C * N; q += blockDim.x) v[q] = xs[q] > 0;
+    __syncthreads();
+    const KitaevOut o = kitaev_weight_block(v, C, L, Jx, Jy, Jz, 1.0 / T[blockIdx.x], A, A + N * (N + 1) / 2,
+                                            A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
+                                            A + N * (N + 1) / 2 + 3 * N, red);
+    if (threadIdx.x == 0) S[blockIdx.x] = o.S;
+}
+
+size_t kitaev_weight_lds(int C, int L) { return 64 * 8 + kitaev_lds_bytes(L) + (size_t)C * L * L + 16; }
+
+hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, double Jx, double Jy, double Jz, const double* T,
+                                double* S, hipStream_t s)
+{
+    hipLaunchKernelGGL(kitaev_weight_kernel, dim3(B), dim3(256), kitaev_weight_lds(C, L), s, x, C, L, Jx, Jy, Jz, T, S);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Backward of F.  Stage 1 (one workgroup per sample b): sigma(a) of every
+// hidden unit (float32 pre-activation, FP64 sigmoid, stored as float), then one
+// thread per parameter p forms g_b dF(x_b)/dtheta_p in FP64 into
+// part[b][p].  Stage 2: out[p] = sum_b part[b][p] in sample order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, const float* __restrict__ hb, int K,
+                                                   int C, int LW, const int8_t* __restrict__ x, int L,
+                                                   const float* __restrict__ gF, double* __restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int LL = L * L, nW = K * C * LW * LW, P = nW + K + C;
+    float* Ws = (float*)smem;
+    float* sg = Ws + nW;
+    uint8_t* v = (uint8_t*)(sg + K * LL);
+    const int8_t* xs = x + (size_t)blockIdx.x * C * LL;
+    for (int q = threadIdx.x; q < nW; q += blockDim.x) Ws[q] = W[q];
+    for (int q = threadIdx.x; q < C * LL; q += blockDim.x) v[q] = xs[q] > 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
+        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
+        float acc = hb[k];
+        for (int c = 0; c < C; ++c)
+            for (int a = 0; a < LW; ++a) {
+                int ia = i + a;
+                if (ia >= L) ia -= L;
+                const uint8_t* row = v + (c * L + ia) * L;
+                const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+                for (int b = 0; b < LW; ++b) {
+                    int jb = j + b;
+                    if (jb >= L) jb -= L;
+                    acc = fmaf(wr[b], (float)row[jb], acc);
+                }
+            }
+        sg[q] = (float)(1.0 / (1.0 + exp(-(double)acc)));
+    }
+    __syncthreads();
+    const double gb = (double)gF[blockIdx.x];
+    double* out = part + (size_t)blockIdx.x * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        double s = 0.0;
+        if (p < nW) {
+            const int b = p % LW, a = (p / LW) % LW, c = (p / (LW * LW)) % C, k = p / (C * LW * LW);
+            const float* sk = sg + k * LL;
+            for (int i = 0; i < L; ++i) {
+                int ia = i + a;
+                if (ia >= L) ia -= L;
+                const uint8_t* row = v + (c * L + ia) * L;
+                const float* srow = sk + i * L;
+                for (int j = 0; j < L; ++j) {
+                    int jb = j + b;
+                    if (jb >= L) jb -= L;
+                    s += row[jb] ? (double)srow[j] : 0.0;
+                }
+            }
+        } else if (p < nW + K) {
+            const float* sk = sg + (p - nW) * LL;
+            for (int q = 0; q < LL; ++q) s += (double)sk[q];
+        } else {
+            const uint8_t* vc = v + (p - nW - K) * LL;
+            for (int q = 0; q < LL; ++q) s += (double)vc[q];
+        }
+        out[p] = -gb * s;
+    }
+}
+
+__global__ __launch_bounds__(256) void grad_stage2(const double* __restrict__ part, int B, int P, int nW, int K,
+                                                   float* __restrict__ dW, float* __restrict__ dhb,
+                                                   float* __restrict__ dvb)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += part[(size_t)b * P + p];
+    if (p < nW) dW[p] = (float)s;
+    else if (p < nW + K) dhb[p - nW] = (float)s;
+    else dvb[p - nW - K] = (float)s;
+}
+
+size_t grad_lds(int K, int C, int LW, int L)
+{
+    return (size_t)(K * C * LW * LW) * 4 + (size_t)K * L * L * 4 + (size_t)C * L * L + 16;
+}
+
+hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, const int8_t* x, int B, int L,
+                       const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s)
+{
+    const int P = K * C * LW * LW + K + C;
+    if (B > 0) {
+        hipLaunchKernelGGL(grad_stage1, dim3(B), dim3(256), grad_lds(K, C, LW, L), s, W, hb, K, C, LW, x, L, gF, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(grad_stage2, dim3((P + 255) / 256), dim3(256), 0, s, part, B, P, K * C * LW * LW, K, dW, dhb,
+                       dvb);
+    return hipGetLastError();
+}
+
+}  // namespace crbm

@@ -1,0 +1,43 @@
+// sweep_common.h -- job descriptors shared by the sweep kernels and the host
+// side of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace crbm {
+
+// One job as the kernels see it; lives in the job's device workspace.
+struct JobDev {
+    const float* W;
+    const float* hb;
+    const float* vb;
+    const double* T;
+    int8_t* state;
+    ChainRec* rec;
+    double J0, J1, J2;
+    uint64_t seed;
+    int K, C, LW, target, L, n_chains, gibbs_k, burnin;
+    uint32_t chain_offset;
+    int init_state;
+};
+
+constexpr int MAX_JOBS_PER_LAUNCH = 128;
+enum : int { MODE_SWEEP = 0, MODE_INIT = 1 };
+
+// Kernel argument block of one launch: blocks [block_begin[j], block_begin[j+1])
+// belong to job j, one block (or one block slice) per chain.
+struct SweepLaunch {
+    const JobDev* jobs[MAX_JOBS_PER_LAUNCH];
+    int block_begin[MAX_JOBS_PER_LAUNCH + 1];
+    int n_jobs;
+    int n_sweeps;
+    int mode;
+    int pad;
+};
+
+size_t generic_lds_bytes(int K, int C, int LW, int L, int target);
+hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);
+
+}  // namespace crbm

@@ -1,0 +1,405 @@
+// sweep_generic.hip -- generic fused propose+accept sweep for gfx950.
+//
+// One workgroup owns one chain for the whole launch: the chain's lattice, the
+// Gibbs intermediates and the filters sit in LDS, so HBM is touched only to
+// load the state at the start and to store it at the end.  A sweep is
+//   - gibbs_k block-Gibbs steps (App. B): hidden pass v -> h and visible pass
+//     h -> v' of the convolutional conditionals, float32 pre-activations with a
+//     guarded Bernoulli test (FP64 re-evaluation inside the error band);
+//   - F(v') of Eq. (free-energy_CRBM) in FP64;
+//   - the target: Ising E(v') (integer) or the Kitaev weight S(v') (FP64
+//     eigen-step, kitaev_eig.h);
+//   - the MH test of Eq. (acceptance) with the CRBM as the second replica;
+//   - the observables of the state after the sweep.
+// The lattice is stored one byte per unit here, which supports every L, C and
+// filter size; the bit-packed kernel in sweep_ising.hip is the fast path for
+// the Ising workloads.
+#include "device_common.h"
+#include "kitaev_eig.h"
+#include "sweep_common.h"
+
+namespace crbm {
+
+struct GenericLds {
+    // byte offsets inside dynamic LDS
+    int off_red, off_W, off_hb, off_vb, off_dah, off_dav, off_v, off_h, off_kit, total;
+};
+
+__host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, int L, int target)
+{
+    GenericLds g;
+    const int LL = L * L;
+    int o = 0;
+    auto al = [](int x, int a) { return (x + a - 1) / a * a; };
+    g.off_red = o;
+    o += 64 * 8;
+    g.off_W = o;
+    o += al(K * C * LW * LW * 4, 16);
+    g.off_hb = o;
+    o += al(K * 4, 16);
+    g.off_vb = o;
+    o += al(C * 4, 16);
+    g.off_dah = o;
+    o += al(K * 4, 16);
+    g.off_dav = o;
+    o += al(C * 4, 16);
+    g.off_v = o;
+    o += al(3 * C * LL, 16);
+    g.off_h = o;
+    o += al(K * LL, 16);
+    g.off_kit = o;
+    if (target == 1) o += (int)kitaev_lds_bytes(L);
+    g.total = al(o, 16);
+    return g;
+}
+
+// FP64 hidden pre-activation of unit (k, i, j)
+__device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* hbs, const uint8_t* v, int K, int C,
+                                                  int LW, int L, int k, int i, int j)
+{
+    (void)K;
+    double acc = (double)hbs[k];
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < LW; ++a) {
+            int ia = i + a;
+            if (ia >= L) ia -= L;
+            const uint8_t* row = v + (c * L + ia) * L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            for (int b = 0; b < LW; ++b) {
+                int jb = j + b;
+                if (jb >= L) jb -= L;
+                acc += (double)wr[b] * (double)row[jb];
+            }
+        }
+    return acc;
+}
+
+__device__ __forceinline__ double preact_visible_d(const float* Ws, const float* vbs, const uint8_t* h, int K, int C,
+                                                   int LW, int L, int c, int x, int y)
+{
+    double acc = (double)vbs[c];
+    for (int k = 0; k < K; ++k)
+        for (int a = 0; a < LW; ++a) {
+            int xa = x - a;
+            if (xa < 0) xa += L;
+            const uint8_t* row = h + (k * L + xa) * L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            for (int b = 0; b < LW; ++b) {
+                int yb = y - b;
+                if (yb < 0) yb += L;
+                acc += (double)wr[b] * (double)row[yb];
+            }
+        }
+    return acc;
+}
+
+// float32 pre-activations (the fast path of the Bernoulli tests)
+__device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* hbs, const uint8_t* v, int C, int LW,
+                                                 int L, int k, int i, int j)
+{
+    float acc = hbs[k];
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < LW; ++a) {
+            int ia = i + a;
+            if (ia >= L) ia -= L;
+            const uint8_t* row = v + (c * L + ia) * L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            for (int b = 0; b < LW; ++b) {
+                int jb = j + b;
+                if (jb >= L) jb -= L;
+                acc = fmaf(wr[b], (float)row[jb], acc);
+            }
+        }
+    return acc;
+}
+
+__device__ __forceinline__ float preact_visible_f(const float* Ws, const float* vbs, const uint8_t* h, int K, int C,
+                                                  int LW, int L, int c, int x, int y)
+{
+    float acc = vbs[c];
+    for (int k = 0; k < K; ++k)
+        for (int a = 0; a < LW; ++a) {
+            int xa = x - a;
+            if (xa < 0) xa += L;
+            const uint8_t* row = h + (k * L + xa) * L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            for (int b = 0; b < LW; ++b) {
+                int yb = y - b;
+                if (yb < 0) yb += L;
+                acc = fmaf(wr[b], (float)row[yb], acc);
+            }
+        }
+    return acc;
+}
+
+// F(v) in FP64 over the workgroup (all threads receive it)
+__device__ double free_energy_block(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v, int K,
+                                    int C, int LW, int L, double* red)
+{
+    const int LL = L * L;
+    double fl = 0.0;
+    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
+        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
+        fl -= softplus_d(preact_hidden_d(Ws, hbs, v, K, C, LW, L, k, i, j));
+    }
+    for (int q = threadIdx.x; q < C * LL; q += blockDim.x) fl -= (double)vbs[q / LL] * (double)v[q];
+    return block_sum(fl, red);
+}
+
+// Ising E/J and M of v (C = 1), over the workgroup
+__device__ void ising_em_block(const uint8_t* v, int L, long long* red, long long& E, long long& M)
+{
+    long long el = 0, ml = 0;
+    for (int q = threadIdx.x; q < L * L; q += blockDim.x) {
+        const int i = q / L, j = q - i * L;
+        const int s = 2 * (int)v[q] - 1;
+        const int sd = 2 * (int)v[(i + 1 == L ? 0 : i + 1) * L + j] - 1;
+        const int sr = 2 * (int)v[i * L + (j + 1 == L ? 0 : j + 1)] - 1;
+        el -= s * (sd + sr);
+        ml += s;
+    }
+    E = block_sum(el, red);
+    M = block_sum(ml, red);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int jb = 0;
+    while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
+    const JobDev& J = *P.jobs[jb];
+    const int g = (int)blockIdx.x - P.block_begin[jb];
+    if (g >= J.n_chains) return;
+
+    const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L;
+    const int tid = threadIdx.x;
+    const GenericLds lay = generic_lds_layout(K, C, LW, L, J.target);
+    double* red = (double*)(smem + lay.off_red);
+    long long* redi = (long long*)(smem + lay.off_red);
+    float* Ws = (float*)(smem + lay.off_W);
+    float* hbs = (float*)(smem + lay.off_hb);
+    float* vbs = (float*)(smem + lay.off_vb);
+    float* dAh = (float*)(smem + lay.off_dah);
+    float* dAv = (float*)(smem + lay.off_dav);
+    uint8_t* vb3 = (uint8_t*)(smem + lay.off_v);
+    uint8_t* h = (uint8_t*)(smem + lay.off_h);
+    double* kit = (double*)(smem + lay.off_kit);
+
+    const int nW = K * C * LW * LW;
+    for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
+    for (int q = tid; q < K; q += NT) hbs[q] = J.hb[q];
+    for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
+    __syncthreads();
+    // error bounds of the float32 pre-activations (recursive fma summation)
+    for (int k = tid; k < K; k += NT) {
+        float s = fabsf(hbs[k]);
+        for (int q = 0; q < C * LW * LW; ++q) s += fabsf(Ws[k * C * LW * LW + q]);
+        dAh[k] = gamma_f32(C * LW * LW + 2) * s * 1.001f;
+    }
+    for (int c = tid; c < C; c += NT) {
+        float s = fabsf(vbs[c]);
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < LW * LW; ++q) s += fabsf(Ws[(k * C + c) * LW * LW + q]);
+        dAv[c] = gamma_f32(K * LW * LW + 2) * s * 1.001f;
+    }
+
+    const uint32_t gid = J.chain_offset + (uint32_t)g;
+    const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+    int8_t* state = J.state + (size_t)g * C * LL;
+    ChainRec* rec = J.rec + g;
+
+    // load or generate the state
+    uint8_t* vcur0 = vb3;
+    if (P.mode == MODE_INIT && J.init_state) {
+        for (int q = tid; q < C * LL; q += NT) {
+            const u32x4 r = philox10((uint32_t)q >> 2, 0u, gid, STREAM_INIT, k0, k1);
+            const uint32_t x = word_of(r, q & 3);
+            const int8_t s = (x >> 31) ? (int8_t)1 : (int8_t)-1;
+            state[q] = s;
+            vcur0[q] = s > 0;
+        }
+    } else {
+        for (int q = tid; q < C * LL; q += NT) vcur0[q] = state[q] > 0;
+    }
+    __syncthreads();
+
+    const double T = J.T[g];
+    const double beta = 1.0 / T;
+    const bool ising = J.target == 0;
+
+    if (P.mode == MODE_INIT) {
+        const double F = free_energy_block(Ws, hbs, vbs, vcur0, K, C, LW, L, red);
+        long long E = 0, M = 0;
+        KitaevOut ko{0.0, 0.0, 0.0};
+        if (ising) ising_em_block(vcur0, L, redi, E, M);
+        else {
+            double* A = kit;
+            const int N = LL;
+            ko = kitaev_weight_block(vcur0, C, L, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
+                                     A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
+                                     A + N * (N + 1) / 2 + 3 * N, red);
+        }
+        if (tid == 0) {
+            ChainRec R{};
+            R.E = E;
+            R.F = F;
+            R.S = ko.S;
+            R.Ef = ko.Ef;
+            R.Cf = ko.Cf;
+            *rec = R;
+        }
+        return;
+    }
+
+    // ---------------------------------------------------------------- sweeps
+    __shared__ long long sh_t0;
+    __shared__ int sh_acc;
+    __shared__ long long sh_M;
+    ChainRec R;
+    if (tid == 0) {
+        R = *rec;
+        sh_t0 = R.sweeps;
+    }
+    long long Mcur = 0;
+    if (ising) {
+        long long Ed;
+        ising_em_block(vcur0, L, redi, Ed, Mcur);
+    } else {
+        __syncthreads();
+    }
+    const uint32_t t0 = (uint32_t)sh_t0;
+    int cur = 0;
+    int nre = 0;
+    for (int it = 0; it < P.n_sweeps; ++it) {
+        const uint32_t t = t0 + (uint32_t)it;
+        int src = cur;
+        for (int sub = 0; sub < J.gibbs_k; ++sub) {
+            int dst = (src + 1) % 3;
+            if (dst == cur) dst = (dst + 1) % 3;
+            const uint8_t* vs = vb3 + src * C * LL;
+            uint8_t* vd = vb3 + dst * C * LL;
+            // hidden pass
+            const int nh = K * LL, ngh = (nh + 3) >> 2;
+            for (int gi = tid; gi < ngh; gi += NT) {
+                const u32x4 r = philox10((uint32_t)gi, t, gid, STREAM_HID | ((uint32_t)sub << 8), k0, k1);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int q = 4 * gi + w;
+                    if (q < nh) {
+                        const int k = q / LL, rr = q - k * LL, i = rr / L, j = rr - i * L;
+                        const float a = preact_hidden_f(Ws, hbs, vs, C, LW, L, k, i, j);
+                        bool near;
+                        bool on = bernoulli_fast(a, word_of(r, w), dAh[k], near);
+                        if (near) {
+                            on = bernoulli_exact(preact_hidden_d(Ws, hbs, vs, K, C, LW, L, k, i, j), word_of(r, w));
+                            ++nre;
+                        }
+                        h[q] = on;
+                    }
+                }
+            }
+            __syncthreads();
+            // visible pass
+            const int nv = C * LL, ngv = (nv + 3) >> 2;
+            for (int gi = tid; gi < ngv; gi += NT) {
+                const u32x4 r = philox10((uint32_t)gi, t, gid, STREAM_VIS | ((uint32_t)sub << 8), k0, k1);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int q = 4 * gi + w;
+                    if (q < nv) {
+                        const int c = q / LL, rr = q - c * LL, x = rr / L, y = rr - x * L;
+                        const float b = preact_visible_f(Ws, vbs, h, K, C, LW, L, c, x, y);
+                        bool near;
+                        bool on = bernoulli_fast(b, word_of(r, w), dAv[c], near);
+                        if (near) {
+                            on = bernoulli_exact(preact_visible_d(Ws, vbs, h, K, C, LW, L, c, x, y), word_of(r, w));
+                            ++nre;
+                        }
+                        vd[q] = on;
+                    }
+                }
+            }
+            __syncthreads();
+            src = dst;
+        }
+        const uint8_t* vp = vb3 + src * C * LL;
+        const double Fp = free_energy_block(Ws, hbs, vbs, vp, K, C, LW, L, red);
+        long long Ep = 0, Mp = 0;
+        KitaevOut ko{0.0, 0.0, 0.0};
+        if (ising) ising_em_block(vp, L, redi, Ep, Mp);
+        else {
+            double* A = kit;
+            const int N = LL;
+            ko = kitaev_weight_block(vp, C, L, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
+                                     A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
+                                     A + N * (N + 1) / 2 + 3 * N, red);
+        }
+        if (tid == 0) {
+            const double logr = ising ? (-beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F)) : ((ko.S - R.S) + (Fp - R.F));
+            const double lu = log(mh_uniform(J.seed, t, gid));
+            const int acc = lu < logr;
+            sh_acc = acc;
+            if (acc) {
+                R.F = Fp;
+                R.E = Ep;
+                R.S = ko.S;
+                R.Ef = ko.Ef;
+                R.Cf = ko.Cf;
+                R.n_acc += 1;
+                sh_M = Mp;
+            } else {
+                sh_M = Mcur;
+            }
+            R.sweeps += 1;
+            if ((long long)t >= (long long)J.burnin) {
+                R.n_meas += 1;
+                if (ising) {
+                    const long long m = sh_M;
+                    R.sumE += R.E;
+                    R.sumE2 += R.E * R.E;
+                    R.sumM += m;
+                    R.sumAbsM += m < 0 ? -m : m;
+                    R.sumM2 += m * m;
+                } else {
+                    R.kE += R.Ef;
+                    R.kE2 += R.Ef * R.Ef;
+                    R.kCf += R.Cf;
+                }
+            }
+        }
+        __syncthreads();
+        if (sh_acc) {
+            cur = src;
+            Mcur = Mp;
+        }
+    }
+    // store the state and the record
+    const uint8_t* vc = vb3 + cur * C * LL;
+    for (int q = tid; q < C * LL; q += NT) state[q] = vc[q] ? (int8_t)1 : (int8_t)-1;
+    const int tot = block_sum(nre, (int*)redi);
+    if (tid == 0) {
+        R.n_recheck += tot;
+        *rec = R;
+    }
+}
+
+template __global__ void sweep_generic_kernel<256>(SweepLaunch);
+template __global__ void sweep_generic_kernel<64>(SweepLaunch);
+
+size_t generic_lds_bytes(int K, int C, int LW, int L, int target)
+{
+    return (size_t)generic_lds_layout(K, C, LW, L, target).total;
+}
+
+hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
+{
+    if (nt == 64) {
+        hipLaunchKernelGGL(sweep_generic_kernel<64>, dim3(n_blocks), dim3(64), lds, s, P);
+    } else {
+        hipLaunchKernelGGL(sweep_generic_kernel<256>, dim3(n_blocks), dim3(256), lds, s, P);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace crbm

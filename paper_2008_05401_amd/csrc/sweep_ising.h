@@ -1,0 +1,14 @@
+// sweep_ising.h -- the bit-packed Ising fast path (sweep_ising.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sweep_common.h"
+
+namespace crbm {
+
+bool ising_fast_supported(int K, int LW, int L);
+int ising_fast_threads(int L);
+size_t ising_fast_lds_bytes(int K, int LW, int L);
+hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int n_blocks, size_t lds, int nt, hipStream_t s);
+
+}  // namespace crbm

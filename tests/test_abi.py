@@ -1,0 +1,104 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/crbm.h declares, and its host-side validation rejects bad arguments
+with the documented status codes before any device work."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2008_05401_amd import _lib
+    try:
+        return _lib, _lib.load()
+    except ImportError as e:  # pragma: no cover - build() runs before the suite
+        pytest.fail(str(e))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"CRBM_API\s+[\w\s\*]+?\b(\w+)\s*\(", src)
+    return names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    _lib, L = lib
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) >= set(_lib.EXPORTS)
+
+
+def test_version(lib):
+    _lib, _ = lib
+    assert "gfx950" in _lib.crbm_version()
+
+
+def _params(K=4, C=1, Lw=3, ptr=0x1000):
+    from paper_2008_05401_amd import _lib
+    return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr)
+
+
+def _desc(target=0, L=8, n=4, gk=1):
+    from paper_2008_05401_amd import _lib
+    return _lib.crbm_batch_desc(target, L, n, gk, 0, 1, 0, 0, 0, (ct.c_double * 3)(1, 1, 1),
+                                0x1000, 0x1000, 0x1000, 1 << 20)
+
+
+def test_workspace_size_validation(lib):
+    _lib, _ = lib
+    assert _lib.crbm_workspace_size(_params(), _desc()) >= 4 * 160
+    assert _lib.crbm_workspace_size(_params(Lw=9), _desc()) == 0          # Lw > 8
+    assert _lib.crbm_workspace_size(_params(Lw=5), _desc(L=4)) == 0       # Lw > L
+    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=0)) == 0   # Ising needs C = 1
+    assert _lib.crbm_workspace_size(_params(C=2), _desc()) == 0
+    assert _lib.crbm_workspace_size(_params(K=65), _desc()) == 0
+    assert _lib.crbm_workspace_size(_params(), _desc(n=0)) == 0
+    assert _lib.crbm_workspace_size(_params(), _desc(gk=0)) == 0
+    assert _lib.crbm_workspace_size(_params(), _desc(L=257)) == 0
+    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=13)) == 0
+
+
+def test_init_rejects_before_device_work(lib):
+    _lib, L = lib
+    ctx = ct.c_void_p()
+    st = L.crbm_init(ct.byref(ctx), ct.byref(_params(Lw=5)), ct.byref(_desc(L=4)), None)
+    assert st == _lib.CRBM_EINVAL and ctx.value is None
+    assert "Lw" in _lib.crbm_last_error()
+    d = _desc()
+    d.workspace_bytes = 16
+    st = L.crbm_init(ct.byref(ctx), ct.byref(_params()), ct.byref(d), None)
+    assert st == _lib.CRBM_EBUDGET
+    st = L.crbm_init(ct.byref(ctx), ct.byref(_params(C=3)), ct.byref(_desc(target=1, L=16)), None)
+    assert st == _lib.CRBM_EUNSUPPORTED
+
+
+def test_other_entry_points_validate(lib):
+    _lib, L = lib
+    p = _params()
+    assert L.crbm_free_energy(ct.byref(p), None, -1, 8, None, None) == _lib.CRBM_EINVAL
+    assert L.crbm_free_energy(ct.byref(p), None, 0, 8, None, None) == _lib.CRBM_OK   # empty batch
+    J = (ct.c_double * 3)(1, 1, 1)
+    assert L.target_energy(0, None, 1, 3, 8, J, None, None, None, None) == _lib.CRBM_EINVAL
+    assert L.target_energy(7, None, 1, 1, 8, J, None, None, None, None) == _lib.CRBM_EINVAL
+    assert L.target_energy(1, None, 1, 3, 13, J, None, None, None, None) == _lib.CRBM_EUNSUPPORTED
+    assert L.crbm_grad_workspace_size(ct.byref(p), 10) >= 10 * (36 + 4 + 1) * 8
+    assert L.crbm_grad(ct.byref(p), None, 1, 8, None, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EINVAL
+    assert L.crbm_grad(ct.byref(p), 0x1000, 1, 8, 0x1000, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EBUDGET
+    assert L.crbm_propose_accept(None, 1) == _lib.CRBM_EINVAL
+    assert L.crbm_propose_accept_many(None, 1, 1) == _lib.CRBM_EINVAL
+
+
+def test_stats_record_layout(lib):
+    _lib, _ = lib
+    assert _lib.STATS_DTYPE.itemsize == 160
+    assert np.dtype(_lib.STATS_DTYPE).names[:4] == ("sweeps", "n_acc", "n_meas", "n_recheck")
