@@ -1,0 +1,170 @@
+"""Benchmark of the CRBM-proposal + MH sweep on one MI355X.
+
+Workload (batched Ising, the configuration the headline metric is quoted on):
+L = 64 periodic square lattice, J = 1, CRBM with K = 8 hidden channels of 5x5
+float32 filters ~ N(0, 0.05) (seed 0, biases 0), 4096 chains over 32
+temperatures linspace(1.5, 3.5) (128 chains each), accumulators on (burn-in
+10% of the timed sweeps).  One step = one propose+accept sweep of every chain
+(steps 1-5 of the sweep: Gibbs proposal, F(x'), integer E(x'), MH test,
+observables).  Steps are launched in blocks of `--block` sweeps per kernel
+launch; the chains stay resident on the GPU between launches.
+
+Printed: one JSON line with throughput (site-sweeps per second, every
+completed propose+MH sweep counted, acceptance rate beside it), the roofline
+of the sweep kernel measured with HIP events on its stream, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X published peaks used for the roofline
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def conv_flops_per_site_sweep(K, C, Lw, gibbs_k=1):
+    """Algorithmic FP32 flops of one sweep per lattice site: the convolutions
+    v->h and h->v' (gibbs_k times) and v'->a' for F(x'), K*C*Lw^2
+    multiply-adds each, 2 flops per multiply-add."""
+    return 2.0 * K * C * Lw * Lw * (2 * gibbs_k + 1)
+
+
+def cpu_baseline(f, T, L, seed, seconds=15.0):
+    import oracle
+    oracle.build(force=False)
+    m = oracle.CRBM(f.W, f.hbias, f.vbias)
+    n = 256
+    ch = oracle.Chains(m, oracle.ISING, L, T[:n], seed=seed)
+    t0 = time.perf_counter()
+    ch.run(1)
+    one = time.perf_counter() - t0
+    sweeps = max(1, int(seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    ch.run(sweeps)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n * L * L * sweeps / dt,
+        "unit": "site-sweeps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"chains 0-{n - 1} of the 4096-chain L=64 batch (T=1.5 and 1.565), {sweeps} sweeps after 1 "
+                  f"untimed sweep, FP64 C oracle with OpenMP over chains, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--block", type=int, default=100, help="sweeps per kernel launch")
+    ap.add_argument("--chains", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); chains are independent, so the "
+              f"path shards across GPUs without communication, but this build measures one GPU only.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2008_05401_amd import api, workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    L, K, C, Lw = 64, 8, 1, 5
+    n = args.chains
+    seed = 0
+    f = WL.random_filters(K, C, Lw, 0.05, seed=seed)
+    T = WL.ising_temperatures_linspace(32, 1.5, 3.5, n)
+    burnin = args.warmup + args.steps // 10
+    job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=seed, burnin=burnin)
+
+    def run(total):
+        done = 0
+        while done < total:
+            b = min(args.block, total - done)
+            job.run(b)
+            done += b
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    launches = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        b = min(args.block, args.steps - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        job.run(b)
+        e1.record(stream)
+        launches.append((b, e0, e1))
+        done += b
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = job.stats()
+
+    # per-launch kernel time from HIP events on the launch stream
+    full = [(b, e0.elapsed_time(e1) * 1e-3) for (b, e0, e1) in launches if b == args.block]
+    if not full:
+        full = [(b, e0.elapsed_time(e1) * 1e-3) for (b, e0, e1) in launches]
+    avg_launch_s = float(np.mean([d for _, d in full]))
+    sweeps_per_launch = full[0][0]
+    flops_per_launch = conv_flops_per_site_sweep(K, C, Lw) * n * L * L * sweeps_per_launch
+    achieved_tflops = flops_per_launch / avg_launch_s / 1e12
+
+    site_sweeps = n * L * L * args.steps
+    value = site_sweeps / wall
+    acc = float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
+    out = {
+        "metric": "MH-accepted CRBM sweeps·sites/sec on 1 GPU",
+        "value": value,
+        "unit": "site-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched Ising L=64, 4096 chains x 32 temperatures in [1.5,3.5], CRBM K=8 5x5 "
+                               "filters ~N(0,0.05), CRBM-Gibbs+MH sweep with E/M/C accumulators",
+                   "L": L, "chains": n, "K": K, "Lw": Lw, "sweeps_per_launch": args.block,
+                   "gibbs_k": 1, "seed": seed},
+        "acceptance": acc,
+        "fp64_rechecks_per_site_sweep": float(st["n_recheck"].sum()) / (n * L * L * (args.steps + args.warmup)),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
+            "traffic": None,
+            "kernel_avg_ms": avg_launch_s * 1e3,
+            "algorithmic_flops_per_site_sweep": conv_flops_per_site_sweep(K, C, Lw),
+            "hbm_algorithmic_GBps": 2.0 * n * L * L / avg_launch_s / 1e9,
+            "hbm_frac": 2.0 * n * L * L / avg_launch_s / 1e9 / PEAK_HBM_GBS,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(f, T, L, seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

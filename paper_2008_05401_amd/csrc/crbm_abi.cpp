@@ -216,11 +216,22 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
         delete c;
         return hip_fail(e, "hipMemcpyAsync(job)");
     }
-    crbm_ctx* one[1] = {c};
-    st = launch_jobs(one, 1, 0, MODE_INIT);
-    if (st != CRBM_OK) {
+    SweepLaunch P;
+    memset(&P, 0, sizeof P);
+    P.jobs[0] = c->job_dev;
+    P.block_begin[0] = 0;
+    P.block_begin[1] = desc->n_chains;
+    P.n_jobs = 1;
+    P.mode = MODE_INIT;
+    const size_t lds = init_lds(params->K, params->C, params->Lw, desc->L, desc->target);
+    if (lds > kLdsLimit) {
         delete c;
-        return st;
+        return fail(CRBM_EUNSUPPORTED, "initialisation needs %zu bytes of LDS", lds);
+    }
+    e = launch_init(P, desc->n_chains, lds, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "init launch");
     }
     *out = c;
     return CRBM_OK;

@@ -1,0 +1,92 @@
+// init.hip -- per-chain set-up of a job: optional initial state from the INIT
+// Philox stream (i.i.d. +-1, as the Binomial(p=0.5) start of Alg. 1), the FP64
+// CRBM free energy of the state and its target (Ising E, M or Kitaev S, E_f,
+// C_f); sums zeroed.  One workgroup per chain, byte-per-unit lattice in LDS.
+#include "device_common.h"
+#include "generic_blocks.h"
+#include "kitaev_eig.h"
+#include "sweep_common.h"
+
+namespace crbm {
+
+__host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, int target)
+{
+    size_t o = 64 * 8;
+    o += ((size_t)K * C * LW * LW + K + C) * 4;
+    o = (o + 15) / 16 * 16;
+    o += (size_t)C * L * L;
+    o = (o + 15) / 16 * 16;
+    if (target == 1) o += kitaev_lds_bytes(L);
+    return o;
+}
+
+__global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int jb = 0;
+    while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
+    const JobDev& J = *P.jobs[jb];
+    const int g = (int)blockIdx.x - P.block_begin[jb];
+    if (g >= J.n_chains) return;
+    const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L, nW = K * C * LW * LW;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    double* red = (double*)smem;
+    float* Ws = (float*)(smem + 64 * 8);
+    float* hbs = Ws + nW;
+    float* vbs = hbs + K;
+    size_t o = 64 * 8 + ((size_t)nW + K + C) * 4;
+    o = (o + 15) / 16 * 16;
+    uint8_t* v = smem + o;
+    o += (size_t)C * LL;
+    o = (o + 15) / 16 * 16;
+    double* kit = (double*)(smem + o);
+
+    for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
+    for (int q = tid; q < K; q += NT) hbs[q] = J.hb[q];
+    for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
+    const uint32_t gid = J.chain_offset + (uint32_t)g;
+    const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+    int8_t* state = J.state + (size_t)g * C * LL;
+    if (J.init_state) {
+        for (int q = tid; q < C * LL; q += NT) {
+            const u32x4 r = philox10((uint32_t)q >> 2, 0u, gid, STREAM_INIT, k0, k1);
+            const int8_t s = (word_of(r, q & 3) >> 31) ? (int8_t)1 : (int8_t)-1;
+            state[q] = s;
+            v[q] = s > 0;
+        }
+    } else {
+        for (int q = tid; q < C * LL; q += NT) v[q] = state[q] > 0;
+    }
+    __syncthreads();
+    const double F = free_energy_block(Ws, hbs, vbs, v, K, C, LW, L, red);
+    long long E = 0, M = 0;
+    KitaevOut ko{0.0, 0.0, 0.0};
+    if (J.target == 0) {
+        ising_em_block(v, L, (long long*)red, E, M);
+    } else {
+        const int N = LL;
+        double* A = kit;
+        ko = kitaev_weight_block(v, C, L, J.J0, J.J1, J.J2, 1.0 / J.T[g], A, A + N * (N + 1) / 2,
+                                 A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N, A + N * (N + 1) / 2 + 3 * N,
+                                 red);
+    }
+    if (tid == 0) {
+        ChainRec R{};
+        R.E = E;
+        R.F = F;
+        R.S = ko.S;
+        R.Ef = ko.Ef;
+        R.Cf = ko.Cf;
+        J.rec[g] = R;
+    }
+}
+
+size_t init_lds(int K, int C, int LW, int L, int target) { return init_lds_bytes(K, C, LW, L, target); }
+
+hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_kernel, dim3(n_blocks), dim3(256), lds, s, P);
+    return hipGetLastError();
+}
+
+}  // namespace crbm

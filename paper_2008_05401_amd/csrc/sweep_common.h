@@ -38,6 +38,8 @@ struct SweepLaunch {
 };
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target);
+size_t init_lds(int K, int C, int LW, int L, int target);
+hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s);
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);
 
 }  // namespace crbm

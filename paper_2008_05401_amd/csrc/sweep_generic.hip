@@ -15,6 +15,7 @@
 // filter size; the bit-packed kernel in sweep_ising.hip is the fast path for
 // the Ising workloads.
 #include "device_common.h"
+#include "generic_blocks.h"
 #include "kitaev_eig.h"
 #include "sweep_common.h"
 
@@ -51,115 +52,6 @@ __host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, i
     if (target == 1) o += (int)kitaev_lds_bytes(L);
     g.total = al(o, 16);
     return g;
-}
-
-// FP64 hidden pre-activation of unit (k, i, j)
-__device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* hbs, const uint8_t* v, int K, int C,
-                                                  int LW, int L, int k, int i, int j)
-{
-    (void)K;
-    double acc = (double)hbs[k];
-    for (int c = 0; c < C; ++c)
-        for (int a = 0; a < LW; ++a) {
-            int ia = i + a;
-            if (ia >= L) ia -= L;
-            const uint8_t* row = v + (c * L + ia) * L;
-            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
-                int jb = j + b;
-                if (jb >= L) jb -= L;
-                acc += (double)wr[b] * (double)row[jb];
-            }
-        }
-    return acc;
-}
-
-__device__ __forceinline__ double preact_visible_d(const float* Ws, const float* vbs, const uint8_t* h, int K, int C,
-                                                   int LW, int L, int c, int x, int y)
-{
-    double acc = (double)vbs[c];
-    for (int k = 0; k < K; ++k)
-        for (int a = 0; a < LW; ++a) {
-            int xa = x - a;
-            if (xa < 0) xa += L;
-            const uint8_t* row = h + (k * L + xa) * L;
-            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
-                int yb = y - b;
-                if (yb < 0) yb += L;
-                acc += (double)wr[b] * (double)row[yb];
-            }
-        }
-    return acc;
-}
-
-// float32 pre-activations (the fast path of the Bernoulli tests)
-__device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* hbs, const uint8_t* v, int C, int LW,
-                                                 int L, int k, int i, int j)
-{
-    float acc = hbs[k];
-    for (int c = 0; c < C; ++c)
-        for (int a = 0; a < LW; ++a) {
-            int ia = i + a;
-            if (ia >= L) ia -= L;
-            const uint8_t* row = v + (c * L + ia) * L;
-            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
-                int jb = j + b;
-                if (jb >= L) jb -= L;
-                acc = fmaf(wr[b], (float)row[jb], acc);
-            }
-        }
-    return acc;
-}
-
-__device__ __forceinline__ float preact_visible_f(const float* Ws, const float* vbs, const uint8_t* h, int K, int C,
-                                                  int LW, int L, int c, int x, int y)
-{
-    float acc = vbs[c];
-    for (int k = 0; k < K; ++k)
-        for (int a = 0; a < LW; ++a) {
-            int xa = x - a;
-            if (xa < 0) xa += L;
-            const uint8_t* row = h + (k * L + xa) * L;
-            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
-                int yb = y - b;
-                if (yb < 0) yb += L;
-                acc = fmaf(wr[b], (float)row[yb], acc);
-            }
-        }
-    return acc;
-}
-
-// F(v) in FP64 over the workgroup (all threads receive it)
-__device__ double free_energy_block(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v, int K,
-                                    int C, int LW, int L, double* red)
-{
-    const int LL = L * L;
-    double fl = 0.0;
-    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
-        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        fl -= softplus_d(preact_hidden_d(Ws, hbs, v, K, C, LW, L, k, i, j));
-    }
-    for (int q = threadIdx.x; q < C * LL; q += blockDim.x) fl -= (double)vbs[q / LL] * (double)v[q];
-    return block_sum(fl, red);
-}
-
-// Ising E/J and M of v (C = 1), over the workgroup
-__device__ void ising_em_block(const uint8_t* v, int L, long long* red, long long& E, long long& M)
-{
-    long long el = 0, ml = 0;
-    for (int q = threadIdx.x; q < L * L; q += blockDim.x) {
-        const int i = q / L, j = q - i * L;
-        const int s = 2 * (int)v[q] - 1;
-        const int sd = 2 * (int)v[(i + 1 == L ? 0 : i + 1) * L + j] - 1;
-        const int sr = 2 * (int)v[i * L + (j + 1 == L ? 0 : j + 1)] - 1;
-        el -= s * (sd + sr);
-        ml += s;
-    }
-    E = block_sum(el, red);
-    M = block_sum(ml, red);
 }
 
 template <int NT>
@@ -209,48 +101,14 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     int8_t* state = J.state + (size_t)g * C * LL;
     ChainRec* rec = J.rec + g;
 
-    // load or generate the state
+    // load the state (crbm_init has generated it if asked to)
     uint8_t* vcur0 = vb3;
-    if (P.mode == MODE_INIT && J.init_state) {
-        for (int q = tid; q < C * LL; q += NT) {
-            const u32x4 r = philox10((uint32_t)q >> 2, 0u, gid, STREAM_INIT, k0, k1);
-            const uint32_t x = word_of(r, q & 3);
-            const int8_t s = (x >> 31) ? (int8_t)1 : (int8_t)-1;
-            state[q] = s;
-            vcur0[q] = s > 0;
-        }
-    } else {
-        for (int q = tid; q < C * LL; q += NT) vcur0[q] = state[q] > 0;
-    }
+    for (int q = tid; q < C * LL; q += NT) vcur0[q] = state[q] > 0;
     __syncthreads();
 
     const double T = J.T[g];
     const double beta = 1.0 / T;
     const bool ising = J.target == 0;
-
-    if (P.mode == MODE_INIT) {
-        const double F = free_energy_block(Ws, hbs, vbs, vcur0, K, C, LW, L, red);
-        long long E = 0, M = 0;
-        KitaevOut ko{0.0, 0.0, 0.0};
-        if (ising) ising_em_block(vcur0, L, redi, E, M);
-        else {
-            double* A = kit;
-            const int N = LL;
-            ko = kitaev_weight_block(vcur0, C, L, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
-                                     A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
-                                     A + N * (N + 1) / 2 + 3 * N, red);
-        }
-        if (tid == 0) {
-            ChainRec R{};
-            R.E = E;
-            R.F = F;
-            R.S = ko.S;
-            R.Ef = ko.Ef;
-            R.Cf = ko.Cf;
-            *rec = R;
-        }
-        return;
-    }
 
     // ---------------------------------------------------------------- sweeps
     __shared__ long long sh_t0;

@@ -1,11 +1,529 @@
-// sweep_ising.hip -- bit-packed Ising fast path (placeholder: not yet enabled).
+// sweep_ising.hip -- bit-packed fused propose+accept sweep for Ising jobs
+// (C = 1) on gfx950.
+//
+// Layout.  One workgroup owns one chain for the whole launch.  Every lattice
+// plane (current state, two proposal buffers, K hidden planes) is kept in LDS
+// with one bit per unit: row i of a plane is RS = max(L/32,1)+1 32-bit words,
+// the last word repeating the first (rows with L < 32 hold the row pattern
+// repeated across the word), so that the 32-bit window that starts at any
+// column j0 < L is a funnel shift of two adjacent words.
+//
+// Work split.  A lane handles "quads" of four horizontally adjacent sites
+// (i, 4m..4m+3); for hidden channel k that is exactly one Philox block
+// (counter (((k L + i) L + 4m) >> 2, sweep, chain, tag)), so no random word is
+// wasted.  Quads are dealt in row-major order, so the lanes that share a
+// 32-bit row word are adjacent and their nibbles are OR-combined with lane
+// shuffles before one lane stores the word.
+//
+// Arithmetic.  Because v and h are binary, each filter row a contributes a sum
+// of a subset of its Lw taps; the 2^Lw subset sums are tabulated per (k, a)
+// once per launch (T1 for the visible->hidden correlation, T2 with the taps
+// reversed for the hidden->visible adjoint), so a pre-activation costs Lw
+// table reads instead of Lw^2 multiply-adds.  Pre-activations are float32
+// with rigorous error bounds; a Bernoulli test whose float32 value lies inside
+// its bound is recomputed in FP64 from the bit planes.  F(x') is summed from
+// float32 softplus terms (product form per site: sum_k max(a,0) +
+// log prod_k (1 + e^{-|a|})) with a rigorous bound B'; the MH test is decided
+// in float32/FP64 only when |log r - log u| exceeds the sum of the bounds of
+// F(x') and F(x), otherwise both free energies are recomputed in FP64.
+// E(x') and M(x') are XOR/popcount counts over row words (exact).
+#include "device_common.h"
+#include "sweep_common.h"
 #include "sweep_ising.h"
 
 namespace crbm {
 
-bool ising_fast_supported(int, int, int) { return false; }
-int ising_fast_threads(int) { return 256; }
-size_t ising_fast_lds_bytes(int, int, int) { return 0; }
-hipError_t launch_ising_fast(const SweepLaunch&, int, int, int, size_t, int, hipStream_t) { return hipErrorInvalidValue; }
+namespace {
+
+__device__ __forceinline__ uint32_t window32(const uint32_t* row, int j0)
+{
+    const int w = j0 >> 5;
+    const uint64_t x = (uint64_t)row[w] | ((uint64_t)row[w + 1] << 32);
+    return (uint32_t)(x >> (j0 & 31));
+}
+
+__device__ __forceinline__ int bit_at(const uint32_t* row, int c) { return (int)((row[c >> 5] >> (c & 31)) & 1u); }
+
+__device__ __forceinline__ uint32_t group_or(uint32_t x, int lpw)
+{
+    if (lpw >= 2) x |= (uint32_t)__shfl_xor((int)x, 1, 64);
+    if (lpw >= 4) x |= (uint32_t)__shfl_xor((int)x, 2, 64);
+    if (lpw >= 8) x |= (uint32_t)__shfl_xor((int)x, 4, 64);
+    return x;
+}
+
+// Combine the nibbles of the lanes that share one row word and store it
+// (plus the wrap copy).  Must be called by every lane of the wave.
+__device__ __forceinline__ void store_nibble(uint32_t* plane, int RS, int L, int i, int m, uint32_t nib, bool active)
+{
+    const int lpw = L >= 32 ? 8 : (L >> 2);
+    uint32_t x = active ? (nib << (4 * (m & (lpw - 1)))) : 0u;
+    x = group_or(x, lpw);
+    if (active && (m & (lpw - 1)) == 0) {
+        uint32_t val = x;
+        if (L == 8) {
+            val |= val << 8;
+            val |= val << 16;
+        } else if (L == 16) {
+            val |= val << 16;
+        }
+        uint32_t* row = plane + i * RS;
+        const int w = L >= 32 ? (m >> 3) : 0;
+        row[w] = val;
+        if (w == 0) row[RS - 1] = val;
+    }
+}
+
+// four bits of row i, columns 4m..4m+3
+__device__ __forceinline__ uint32_t quad_bits(const uint32_t* plane, int RS, int L, int i, int m)
+{
+    const uint32_t* row = plane + i * RS;
+    const int w = L >= 32 ? (m >> 3) : 0;
+    const int sh = L >= 32 ? 4 * (m & 7) : 4 * m;
+    return (row[w] >> sh) & 15u;
+}
+
+// E/J = -2L^2 + 2 (unsatisfied bonds) and M = 2 (up spins) - L^2 of a plane
+__device__ void ising_em_bits(const uint32_t* pl, int L, int RS, long long* red, long long& E, long long& M)
+{
+    const int nwr = L >= 32 ? (L >> 5) : 1;
+    const uint32_t mask = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+    long long unsat = 0, ones = 0;
+    for (int t = threadIdx.x; t < L * nwr; t += blockDim.x) {
+        const int i = t / nwr, w = t - (t / nwr) * nwr;
+        const uint32_t* row = pl + i * RS;
+        const uint32_t* dn = pl + (i + 1 == L ? 0 : i + 1) * RS;
+        const uint32_t x = row[w] & mask;
+        const uint32_t right = window32(row, (w << 5) + 1) & mask;
+        unsat += __popc(x ^ right) + __popc((x ^ dn[w]) & mask);
+        ones += __popc(x);
+    }
+    const long long su = block_sum(unsat, red);
+    const long long so = block_sum(ones, red);
+    E = -2LL * L * L + 2LL * su;
+    M = 2LL * so - (long long)L * L;
+}
+
+template <int LW>
+__device__ __forceinline__ double preact_h_exact(const float* __restrict__ W, float hb, const uint32_t* pl, int RS,
+                                                 int L, int k, int i, int j)
+{
+    double acc = (double)hb;
+#pragma unroll
+    for (int a = 0; a < LW; ++a) {
+        int ia = i + a;
+        if (ia >= L) ia -= L;
+        const uint32_t* row = pl + ia * RS;
+#pragma unroll
+        for (int b = 0; b < LW; ++b) {
+            int jb = j + b;
+            if (jb >= L) jb -= L;
+            if (bit_at(row, jb)) acc += (double)W[(k * LW + a) * LW + b];
+        }
+    }
+    return acc;
+}
+
+template <int LW>
+__device__ __forceinline__ double preact_v_exact(const float* __restrict__ W, float vb, const uint32_t* hpl, int PL,
+                                                 int RS, int L, int K, int x, int y)
+{
+    double acc = (double)vb;
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int a = 0; a < LW; ++a) {
+            int xa = x - a;
+            if (xa < 0) xa += L;
+            const uint32_t* row = hpl + k * PL + xa * RS;
+#pragma unroll
+            for (int b = 0; b < LW; ++b) {
+                int yb = y - b;
+                if (yb < 0) yb += L;
+                if (bit_at(row, yb)) acc += (double)W[(k * LW + a) * LW + b];
+            }
+        }
+    return acc;
+}
+
+// FP64 free energy of a bit plane, over the workgroup
+template <int LW>
+__device__ double free_energy_exact(const float* __restrict__ W, const float* hbs, float vb, const uint32_t* pl,
+                                    int RS, int L, int K, double* red)
+{
+    const int LL = L * L;
+    double f = 0.0;
+    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
+        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
+        f -= softplus_d(preact_h_exact<LW>(W, hbs[k], pl, RS, L, k, i, j));
+    }
+    for (int q = threadIdx.x; q < LL; q += blockDim.x) {
+        const int i = q / L, j = q - i * L;
+        if (bit_at(pl + i * RS, j)) f -= (double)vb;
+    }
+    return block_sum(f, red);
+}
+
+}  // namespace
+
+template <int LW, int NT>
+__global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
+{
+    constexpr int NP = 1 << LW;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int jb = 0;
+    while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
+    const JobDev& J = *P.jobs[jb];
+    const int g = (int)blockIdx.x - P.block_begin[jb];
+    if (g >= J.n_chains) return;
+
+    const int K = J.K, L = J.L;
+    const int RS = (L >= 32 ? (L >> 5) : 1) + 1;
+    const int PL = L * RS;
+    const int qpr = L >> 2, nq = (L * L) >> 2;
+    const int nrounds = (nq + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int tsz = K * LW * NP;
+
+    float* T1 = (float*)smem;
+    float* T2 = T1 + tsz;
+    float* hbs = T2 + tsz;
+    float* dAh = hbs + K;
+    double* red = (double*)(smem + (((size_t)(2 * tsz + 2 * K) * 4 + 15) & ~(size_t)15));
+    uint32_t* vpl = (uint32_t*)(red + 64);
+    uint32_t* hpl = vpl + 3 * PL;
+    __shared__ float sh_vb, sh_dAv;
+    __shared__ long long sh_t0;
+    __shared__ int sh_flag;
+
+    const float* __restrict__ W = J.W;
+    // subset-sum tables of every filter row
+    for (int idx = tid; idx < tsz; idx += NT) {
+        const int p = idx & (NP - 1), ka = idx >> LW;
+        const float* wr = W + ka * LW;  // (k * LW + a) * LW with C = 1
+        float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int b = 0; b < LW; ++b) {
+            const float w = wr[b];
+            if ((p >> b) & 1) s1 += w;
+            if ((p >> (LW - 1 - b)) & 1) s2 += w;
+        }
+        T1[idx] = s1;
+        T2[idx] = s2;
+    }
+    for (int k = tid; k < K; k += NT) {
+        const float hb = J.hb[k];
+        float s = fabsf(hb);
+        for (int q = 0; q < LW * LW; ++q) s += fabsf(W[k * LW * LW + q]);
+        hbs[k] = hb;
+        // table entries: <= LW-1 roundings; pre-activation: LW more
+        dAh[k] = gamma_f32(2 * LW + 2) * s * 1.001f;
+    }
+    if (tid == 0) {
+        const float vb = J.vb[0];
+        float s = fabsf(vb);
+        for (int q = 0; q < K * LW * LW; ++q) s += fabsf(W[q]);
+        sh_vb = vb;
+        sh_dAv = gamma_f32(K * LW + LW + 2) * s * 1.001f;
+    }
+
+    const uint32_t gid = J.chain_offset + (uint32_t)g;
+    const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
+    int8_t* state = J.state + (size_t)g * L * L;
+    ChainRec* rec = J.rec + g;
+
+    // load the state into plane 0 (4 int8 per lane; +1 = 0x01, -1 = 0xFF)
+    for (int r = 0; r < nrounds; ++r) {
+        const int Q = r * NT + tid;
+        const bool active = Q < nq;
+        const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+        uint32_t nib = 0;
+        if (active) {
+            const uint32_t w4 = ~*(const uint32_t*)(state + i * L + 4 * m);
+            nib = ((w4 >> 7) & 1u) | ((w4 >> 14) & 2u) | ((w4 >> 21) & 4u) | ((w4 >> 28) & 8u);
+        }
+        store_nibble(vpl, RS, L, i, m, nib, active);
+    }
+    ChainRec R;
+    double Bcur = 0.0;
+    if (tid == 0) {
+        R = *rec;
+        sh_t0 = R.sweeps;
+        Bcur = R.reserved[0];
+    }
+    __syncthreads();
+    long long Ecur_d, Mcur;
+    ising_em_bits(vpl, L, RS, (long long*)red, Ecur_d, Mcur);
+    const double beta = 1.0 / J.T[g];
+    const uint32_t t0 = (uint32_t)sh_t0;
+    const float vb = sh_vb, dAv = sh_dAv;
+    float dAh_sum = 0.f;
+    for (int k = 0; k < K; ++k) dAh_sum += dAh[k];
+
+    int cur = 0;
+    int nre = 0, nre_mh = 0;
+    for (int it = 0; it < P.n_sweeps; ++it) {
+        const uint32_t t = t0 + (uint32_t)it;
+        int src = cur;
+        for (int sub = 0; sub < J.gibbs_k; ++sub) {
+            int dst = (src + 1) % 3;
+            if (dst == cur) dst = (dst + 1) % 3;
+            const uint32_t* vs = vpl + src * PL;
+            uint32_t* vd = vpl + dst * PL;
+            const uint32_t tagh = STREAM_HID | ((uint32_t)sub << 8);
+            const uint32_t tagv = STREAM_VIS | ((uint32_t)sub << 8);
+            // ---- hidden pass: h ~ P(h | v)
+            for (int r = 0; r < nrounds; ++r) {
+                const int Q = r * NT + tid;
+                const bool active = Q < nq;
+                const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+                const int j0 = 4 * m;
+                uint32_t win[LW];
+#pragma unroll
+                for (int a = 0; a < LW; ++a) {
+                    int ia = i + a;
+                    if (ia >= L) ia -= L;
+                    win[a] = window32(vs + ia * RS, j0);
+                }
+                for (int k = 0; k < K; ++k) {
+                    const float* Tk = T1 + k * LW * NP;
+                    const float hk = hbs[k];
+                    float acc[4] = {hk, hk, hk, hk};
+#pragma unroll
+                    for (int a = 0; a < LW; ++a)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((win[a] >> s) & (NP - 1))];
+                    const u32x4 rn = philox10((uint32_t)(((k * L + i) * L + j0) >> 2), t, gid, tagh, k0, k1);
+                    uint32_t nib = 0;
+                    const float dk = dAh[k];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        bool near;
+                        const uint32_t x = word_of(rn, s);
+                        bool on = bernoulli_fast(acc[s], x, dk, near);
+                        if (near && active) {
+                            on = bernoulli_exact(preact_h_exact<LW>(W, hk, vs, RS, L, k, i, j0 + s), x);
+                            ++nre;
+                        }
+                        nib |= (uint32_t)on << s;
+                    }
+                    store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
+                }
+            }
+            __syncthreads();
+            // ---- visible pass: v' ~ P(v | h)
+            for (int r = 0; r < nrounds; ++r) {
+                const int Q = r * NT + tid;
+                const bool active = Q < nq;
+                const int x = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+                const int y0 = 4 * m;
+                int jst = y0 - (LW - 1);
+                if (jst < 0) jst += L;
+                float acc[4] = {vb, vb, vb, vb};
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t* hk = hpl + k * PL;
+                    const float* Tk = T2 + k * LW * NP;
+#pragma unroll
+                    for (int a = 0; a < LW; ++a) {
+                        int xa = x - a;
+                        if (xa < 0) xa += L;
+                        const uint32_t w = window32(hk + xa * RS, jst);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((w >> s) & (NP - 1))];
+                    }
+                }
+                const u32x4 rn = philox10((uint32_t)((x * L + y0) >> 2), t, gid, tagv, k0, k1);
+                uint32_t nib = 0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    bool near;
+                    const uint32_t xr = word_of(rn, s);
+                    bool on = bernoulli_fast(acc[s], xr, dAv, near);
+                    if (near && active) {
+                        on = bernoulli_exact(preact_v_exact<LW>(W, vb, hpl, PL, RS, L, K, x, y0 + s), xr);
+                        ++nre;
+                    }
+                    nib |= (uint32_t)on << s;
+                }
+                store_nibble(vd, RS, L, x, m, nib, active);
+            }
+            __syncthreads();
+            src = dst;
+        }
+        // ---- F(x') with its error bound, E(x'), M(x')
+        const uint32_t* vp = vpl + src * PL;
+        double Floc = 0.0;
+        float bnd = 0.f;
+        for (int r = 0; r < nrounds; ++r) {
+            const int Q = r * NT + tid;
+            const bool active = Q < nq;
+            const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+            const int j0 = 4 * m;
+            uint32_t win[LW];
+#pragma unroll
+            for (int a = 0; a < LW; ++a) {
+                int ia = i + a;
+                if (ia >= L) ia -= L;
+                win[a] = window32(vp + ia * RS, j0);
+            }
+            float msum[4] = {0.f, 0.f, 0.f, 0.f}, prod[4] = {1.f, 1.f, 1.f, 1.f}, asum[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < K; ++k) {
+                const float* Tk = T1 + k * LW * NP;
+                const float hk = hbs[k];
+                float acc[4] = {hk, hk, hk, hk};
+#pragma unroll
+                for (int a = 0; a < LW; ++a)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((win[a] >> s) & (NP - 1))];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float av = fabsf(acc[s]);
+                    msum[s] += fmaxf(acc[s], 0.f);
+                    prod[s] *= 1.0f + __builtin_amdgcn_exp2f(-av * 1.44269504088896341f);
+                    asum[s] += av;
+                }
+            }
+            if (active) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float ss = msum[s] + __builtin_amdgcn_logf(prod[s]) * 0.693147180559945309f;
+                    Floc -= (double)ss;
+                    bnd += (float)(K + 2) * (0x1p-24f * (asum[s] + fabsf(ss)) + 0x1p-19f);
+                }
+            }
+        }
+        const double Fsp = block_sum(Floc, red);
+        const double Bp = block_sum((double)bnd, red) + (double)dAh_sum * L * L;
+        long long Ep, Mp;
+        ising_em_bits(vp, L, RS, (long long*)red, Ep, Mp);
+        const long long ones = (Mp + (long long)L * L) / 2;
+        const double Fp = Fsp - (double)vb * (double)ones;
+        double lu = 0.0;
+        if (tid == 0) {
+            const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
+            lu = log(mh_uniform(J.seed, t, gid));
+            const double band = Bp + Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
+            sh_flag = (fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2;
+        }
+        __syncthreads();
+        int flag = sh_flag;
+        double Fnew = Fp, Bnew = Bp, Fold = 0.0;
+        if (flag == 2) {
+            // inside the float32 band: decide with FP64 free energies of both states
+            Fnew = free_energy_exact<LW>(W, hbs, vb, vp, RS, L, K, red);
+            Fold = free_energy_exact<LW>(W, hbs, vb, vpl + cur * PL, RS, L, K, red);
+            Bnew = 0.0;
+            if (tid == 0) {
+                const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fnew - Fold);
+                sh_flag = lu < logr ? 1 : 0;
+                R.F = Fold;
+                Bcur = 0.0;
+                ++nre_mh;
+            }
+            __syncthreads();
+            flag = sh_flag;
+        }
+        if (tid == 0) {
+            if (flag) {
+                R.F = Fnew;
+                Bcur = Bnew;
+                R.E = Ep;
+                R.n_acc += 1;
+            }
+            R.sweeps += 1;
+            if ((long long)t >= (long long)J.burnin) {
+                const long long mm = flag ? Mp : Mcur;
+                R.n_meas += 1;
+                R.sumE += R.E;
+                R.sumE2 += R.E * R.E;
+                R.sumM += mm;
+                R.sumAbsM += mm < 0 ? -mm : mm;
+                R.sumM2 += mm * mm;
+            }
+        }
+        if (flag) {
+            cur = src;
+            Mcur = Mp;
+        }
+        __syncthreads();
+    }
+    // store the state
+    for (int r = 0; r < nrounds; ++r) {
+        const int Q = r * NT + tid;
+        if (Q < nq) {
+            const int i = Q / qpr, m = Q - (Q / qpr) * qpr;
+            const uint32_t nib = quad_bits(vpl + cur * PL, RS, L, i, m);
+            const uint32_t up = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+            const uint32_t dn = ((~nib) & 1u) | (((~nib) & 2u) << 7) | (((~nib) & 4u) << 14) | (((~nib) & 8u) << 21);
+            *(uint32_t*)(state + i * L + 4 * m) = up | (dn * 0xFFu);
+        }
+    }
+    const int tot = block_sum(nre, (int*)red);
+    if (tid == 0) {
+        R.n_recheck += tot + nre_mh;
+        R.reserved[0] = Bcur;
+        *rec = R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+bool ising_fast_supported(int K, int LW, int L)
+{
+    if (LW < 1 || LW > 6 || LW > L || K < 1 || K > 64) return false;
+    if (!(L == 8 || L == 16 || (L % 32 == 0 && L <= 256))) return false;
+    return ising_fast_lds_bytes(K, LW, L) <= 160 * 1024;
+}
+
+int ising_fast_threads(int L)
+{
+    const int nq = L * L / 4;
+    if (nq <= 64) return 64;
+    if (nq <= 1024) return 256;
+    return 512;
+}
+
+size_t ising_fast_lds_bytes(int K, int LW, int L)
+{
+    const size_t tsz = (size_t)K * LW * ((size_t)1 << LW);
+    size_t o = ((2 * tsz + 2 * (size_t)K) * 4 + 15) & ~(size_t)15;
+    o += 64 * 8;
+    const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
+    o += (3 + (size_t)K) * (size_t)L * RS * 4;
+    return o;
+}
+
+template <int LW>
+static hipError_t launch_lw(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
+{
+    switch (nt) {
+    case 64:
+        hipLaunchKernelGGL((sweep_ising_kernel<LW, 64>), dim3(n_blocks), dim3(64), lds, s, P);
+        break;
+    case 256:
+        hipLaunchKernelGGL((sweep_ising_kernel<LW, 256>), dim3(n_blocks), dim3(256), lds, s, P);
+        break;
+    case 512:
+        hipLaunchKernelGGL((sweep_ising_kernel<LW, 512>), dim3(n_blocks), dim3(512), lds, s, P);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int n_blocks, size_t lds, int nt, hipStream_t s)
+{
+    (void)K;
+    switch (LW) {
+    case 1: return launch_lw<1>(P, n_blocks, lds, nt, s);
+    case 2: return launch_lw<2>(P, n_blocks, lds, nt, s);
+    case 3: return launch_lw<3>(P, n_blocks, lds, nt, s);
+    case 4: return launch_lw<4>(P, n_blocks, lds, nt, s);
+    case 5: return launch_lw<5>(P, n_blocks, lds, nt, s);
+    case 6: return launch_lw<6>(P, n_blocks, lds, nt, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace crbm

@@ -1,0 +1,122 @@
+"""GPU parity of the bit-packed Ising path (L in {8, 16} or a multiple of 32,
+Lw <= 6) against the FP64 oracle: final states, accept counts and integer
+accumulators bit-exact, F to 1e-9 relative (the GPU value is the float32-term
+sum when no re-check happened, bounded by its own error bound)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2008_05401_amd import workloads as WL  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_05401_amd import api as A
+    return A
+
+
+def check_chains(orc, job, ch, f_atol):
+    st = job.stats()
+    assert np.array_equal(job.state.cpu().numpy(), ch.state)
+    for name in ("sweeps", "n_acc", "n_meas", "E", "sumE", "sumE2", "sumM", "sumAbsM", "sumM2"):
+        assert np.array_equal(st[name], ch.rec[name]), name
+    # F of the current state: float32-term sum within its rigorous bound (reserved[0])
+    # (FP64 sums in a different order agree to ~1e-13 relative)
+    bound = st["reserved"][:, 0]
+    tol = bound + f_atol + 1e-11 * np.abs(ch.rec["F"])
+    assert np.all(np.abs(st["F"] - ch.rec["F"]) <= tol), np.abs(st["F"] - ch.rec["F"]).max()
+    assert ch.ties[0] == 0 and ch.ties[1] == 0
+    return st
+
+
+def run_pair(orc, api, f, L, T, seed, sweeps, gibbs_k=1, burnin=0, blocks=None, chain_offset=0):
+    job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=seed, gibbs_k=gibbs_k, burnin=burnin,
+                  chain_offset=chain_offset)
+    ch = orc.Chains(orc.CRBM(f.W, f.hbias, f.vbias), orc.ISING, L, T, seed=seed, gibbs_k=gibbs_k, burnin=burnin,
+                    g0=chain_offset)
+    for b in (blocks or [sweeps]):
+        job.run(b)
+        ch.run(b)
+    return job, ch
+
+
+def test_small_config_full(orc, api):
+    # L=8, K=4 3x3 filters ~ N(0, 0.1), T=2.269, 64 chains x 2000 sweeps, burn-in 10%
+    f = WL.random_filters(4, 1, 3, 0.1, seed=0)
+    job, ch = run_pair(orc, api, f, 8, np.full(64, 2.269), seed=0, sweeps=2000, burnin=200,
+                       blocks=[500, 500, 1000])
+    check_chains(orc, job, ch, 1e-9)
+
+
+@pytest.mark.parametrize("L,K,Lw,gk,n,sweeps", [
+    (16, 8, 5, 1, 32, 30), (32, 8, 5, 1, 16, 10), (32, 4, 1, 1, 8, 20), (32, 2, 6, 2, 8, 10),
+    (32, 3, 2, 1, 8, 12), (32, 5, 4, 3, 4, 6), (64, 8, 5, 2, 8, 4), (128, 8, 5, 1, 4, 2), (256, 8, 5, 1, 2, 2),
+    (16, 1, 3, 1, 64, 40), (8, 8, 6, 2, 16, 25),
+])
+def test_shapes(orc, api, L, K, Lw, gk, n, sweeps):
+    f = WL.random_filters_with_bias(K, 1, Lw, 0.3 / Lw, 0.1, seed=L + K + Lw)
+    T = np.linspace(1.2, 4.0, n)
+    job, ch = run_pair(orc, api, f, L, T, seed=L * 7 + Lw, sweeps=sweeps, gibbs_k=gk, burnin=1)
+    check_chains(orc, job, ch, 1e-9)
+
+
+@pytest.mark.parametrize("L", [16, 64])
+def test_exact_kernel_mh_recheck_path(orc, api, L):
+    # acceptance ~ 1: |log r - log u| is often inside the float32 band, so the
+    # FP64 re-evaluation of both free energies decides
+    T = 2.269
+    f = WL.analytic_ising_filters(T, K=8, Lw=5)
+    job, ch = run_pair(orc, api, f, L, np.full(16, T), seed=3, sweeps=24, burnin=4, blocks=[10, 14])
+    st = check_chains(orc, job, ch, 1e-9)
+    assert st["n_acc"].sum() / st["sweeps"].sum() > 0.9
+    assert st["n_recheck"].sum() > 0
+
+
+def test_batched_config_sampled_chains(orc, api):
+    # full-size batched Ising launch (4096 chains, L=64, K=8 5x5 ~ N(0,0.05)); the oracle
+    # recomputes a sample of chains one by one from their chain index
+    L, n = 64, 4096
+    f = WL.random_filters(8, 1, 5, 0.05, seed=0)
+    T = WL.ising_temperatures_linspace(32, 1.5, 3.5, n)
+    job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=0, burnin=1)
+    job.run(3)
+    st = job.stats()
+    state = job.state.cpu().numpy()
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    for g in (0, 1, 777, 2048, 4095):
+        ch = orc.Chains(m, orc.ISING, L, T[g:g + 1], seed=0, burnin=1, g0=g)
+        ch.run(3)
+        assert np.array_equal(state[g], ch.state[0])
+        for name in ("n_acc", "E", "sumE", "sumM2"):
+            assert st[name][g] == ch.rec[name][0]
+
+
+def test_resume_is_bitwise(api):
+    f = WL.random_filters(8, 1, 5, 0.05, seed=1)
+    T = np.linspace(1.5, 3.5, 32)
+    a = api.Job(api.CRBMParams.from_filters(f), api.ISING, 32, T, seed=9, burnin=3)
+    a.run(12)
+    b = api.Job(api.CRBMParams.from_filters(f), api.ISING, 32, T, seed=9, burnin=3)
+    b.run(5)
+    # checkpoint: state + records; restore into a fresh job and continue
+    saved_state = b.state.clone()
+    saved_rec = b.stats_device().clone()
+    c = api.Job(api.CRBMParams.from_filters(f), api.ISING, 32, T, seed=9, burnin=3, state=saved_state)
+    ws = c.workspace
+    base = (ws.data_ptr() + 255) // 256 * 256 - ws.data_ptr()
+    ws[base + 256: base + 256 + saved_rec.numel()].copy_(saved_rec)
+    c.run(7)
+    assert np.array_equal(a.state.cpu().numpy(), c.state.cpu().numpy())
+    sa, sc = a.stats(), c.stats()
+    for name in ("sweeps", "n_acc", "sumE", "sumE2", "sumM", "E"):
+        assert np.array_equal(sa[name], sc[name])
