@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--chains", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); chains are independent, so the "
@@ -83,6 +85,13 @@ def main():
     from paper_2008_05401_amd import api, workloads as WL
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     L, K, C, Lw = 64, 8, 1, 5
     n = args.chains
     seed = 0
