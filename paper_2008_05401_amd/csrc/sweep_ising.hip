@@ -44,11 +44,13 @@ __device__ __forceinline__ uint32_t window32(const uint32_t* row, int j0)
 
 __device__ __forceinline__ int bit_at(const uint32_t* row, int c) { return (int)((row[c >> 5] >> (c & 31)) & 1u); }
 
+// OR over groups of lpw = 2, 4 or 8 adjacent lanes, result valid in the
+// group's first lane (quad permutations xor 1, xor 2, then row_shl:4)
 __device__ __forceinline__ uint32_t group_or(uint32_t x, int lpw)
 {
-    if (lpw >= 2) x |= (uint32_t)__shfl_xor((int)x, 1, 64);
-    if (lpw >= 4) x |= (uint32_t)__shfl_xor((int)x, 2, 64);
-    if (lpw >= 8) x |= (uint32_t)__shfl_xor((int)x, 4, 64);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    if (lpw >= 4) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+    if (lpw >= 8) x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false);
     return x;
 }
 
@@ -74,6 +76,31 @@ __device__ __forceinline__ void store_nibble(uint32_t* plane, int RS, int L, int
     }
 }
 
+// Set or clear bit (i, c) of a plane, including its copies (wrap word, row
+// pattern repeated across the word for L < 32); atomic so that concurrent
+// fixes of neighbouring bits are safe.
+__device__ __forceinline__ void put_bit(uint32_t* plane, int RS, int L, int i, int c, bool on)
+{
+    uint32_t* row = plane + i * RS;
+    uint32_t mask;
+    int w;
+    if (L >= 32) {
+        w = c >> 5;
+        mask = 1u << (c & 31);
+    } else {
+        w = 0;
+        mask = 0;
+        for (int p = c; p < 32; p += L) mask |= 1u << p;
+    }
+    if (on) {
+        atomicOr(row + w, mask);
+        if (w == 0) atomicOr(row + RS - 1, mask);
+    } else {
+        atomicAnd(row + w, ~mask);
+        if (w == 0) atomicAnd(row + RS - 1, ~mask);
+    }
+}
+
 // four bits of row i, columns 4m..4m+3
 __device__ __forceinline__ uint32_t quad_bits(const uint32_t* plane, int RS, int L, int i, int m)
 {
@@ -86,13 +113,14 @@ __device__ __forceinline__ uint32_t quad_bits(const uint32_t* plane, int RS, int
 // E/J = -2L^2 + 2 (unsatisfied bonds) and M = 2 (up spins) - L^2 of a plane
 __device__ void ising_em_bits(const uint32_t* pl, int L, int RS, long long* red, long long& E, long long& M)
 {
-    const int nwr = L >= 32 ? (L >> 5) : 1;
+    const int lgw = L >= 32 ? (31 - __builtin_clz(L)) - 5 : 0;  // log2(words per row)
+    const int nwr = 1 << lgw;
     const uint32_t mask = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     long long unsat = 0, ones = 0;
     for (int t = threadIdx.x; t < L * nwr; t += blockDim.x) {
-        const int i = t / nwr, w = t - (t / nwr) * nwr;
+        const int i = t >> lgw, w = t & (nwr - 1);
         const uint32_t* row = pl + i * RS;
-        const uint32_t* dn = pl + (i + 1 == L ? 0 : i + 1) * RS;
+        const uint32_t* dn = pl + ((i + 1) & (L - 1)) * RS;
         const uint32_t x = row[w] & mask;
         const uint32_t right = window32(row, (w << 5) + 1) & mask;
         unsat += __popc(x ^ right) + __popc((x ^ dn[w]) & mask);
@@ -129,6 +157,7 @@ __device__ __forceinline__ double preact_v_exact(const float* __restrict__ W, fl
                                                  int RS, int L, int K, int x, int y)
 {
     double acc = (double)vb;
+#pragma unroll 1
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int a = 0; a < LW; ++a) {
@@ -163,12 +192,37 @@ __device__ double free_energy_exact(const float* __restrict__ W, const float* hb
     return block_sum(f, red);
 }
 
+// acc[s] = bias + sum_a T[off[a][s]] as a shallow tree: all LW reads are
+// issued before the first add, so LDS latency is paid once per channel
+template <int LW>
+__device__ __forceinline__ void table_sums(const float* __restrict__ T, const uint32_t (&off)[LW][4], float bias,
+                                           float (&acc)[4])
+{
+    float v[LW][4];
+#pragma unroll
+    for (int a = 0; a < LW; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[a][s] = T[off[a][s]];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float t = v[0][s];
+#pragma unroll
+        for (int a = 1; a + 1 < LW; a += 2) t += v[a][s] + v[a + 1][s];
+        if ((LW & 1) == 0) t += v[LW - 1][s];
+        acc[s] = bias + t;
+    }
+}
+
 }  // namespace
 
-template <int LW, int NT>
-__global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
+// KT > 0: the number of hidden channels is a compile-time constant (loops over
+// channels unrolled, table offsets become instruction immediates); KT == 0:
+// runtime K.  L is a power of two in {8, ..., 256}.
+template <int KT, int LW, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sweep_ising_kernel(SweepLaunch P)
 {
     constexpr int NP = 1 << LW;
+    constexpr int KU = KT > 0 ? KT : 1;  // unroll factor of the channel loops
     extern __shared__ __align__(16) unsigned char smem[];
     int jb = 0;
     while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
@@ -176,10 +230,14 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
     const int g = (int)blockIdx.x - P.block_begin[jb];
     if (g >= J.n_chains) return;
 
-    const int K = J.K, L = J.L;
+    const int K = KT > 0 ? KT : J.K;
+    const int L = J.L;
+    const int lgL = 31 - __builtin_clz(L);
+    const int Lm = L - 1;
     const int RS = (L >= 32 ? (L >> 5) : 1) + 1;
     const int PL = L * RS;
-    const int qpr = L >> 2, nq = (L * L) >> 2;
+    const int lgq = lgL - 2;  // quads per row = L/4
+    const int nq = (L * L) >> 2;
     const int nrounds = (nq + NT - 1) / NT;
     const int tid = threadIdx.x;
     const int tsz = K * LW * NP;
@@ -187,16 +245,25 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
     float* T1 = (float*)smem;
     float* T2 = T1 + tsz;
     float* hbs = T2 + tsz;
-    float* dAh = hbs + K;
-    double* red = (double*)(smem + (((size_t)(2 * tsz + 2 * K) * 4 + 15) & ~(size_t)15));
+    float* dAh = hbs + K;      // [2K]: Bernoulli bands, then S_k
+    float* dApre = dAh + 2 * K;
+    double* red = (double*)(smem + (((size_t)(2 * tsz + 4 * K) * 4 + 15) & ~(size_t)15));
     uint32_t* vpl = (uint32_t*)(red + 64);
     uint32_t* hpl = vpl + 3 * PL;
-    __shared__ float sh_vb, sh_dAv;
+    __shared__ float sh_vb, sh_dAv, sh_vb_raw;
     __shared__ long long sh_t0;
     __shared__ int sh_flag;
+    // units whose float32 Bernoulli test fell inside its error band
+    constexpr int QCAP = 512;
+    __shared__ uint32_t nearq[QCAP];
+    __shared__ int sh_qn;
+    __shared__ ChainRec R;
+    __shared__ double sh_Bcur;
 
     const float* __restrict__ W = J.W;
-    // subset-sum tables of every filter row
+    constexpr float NLOG2E = -1.44269504088896341f;
+    // subset-sum tables of every filter row, scaled by -log2(e) so that the
+    // passes produce z = -a log2(e) directly (exp2(z) = e^{-a})
     for (int idx = tid; idx < tsz; idx += NT) {
         const int p = idx & (NP - 1), ka = idx >> LW;
         const float* wr = W + ka * LW;  // (k * LW + a) * LW with C = 1
@@ -207,23 +274,29 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
             if ((p >> b) & 1) s1 += w;
             if ((p >> (LW - 1 - b)) & 1) s2 += w;
         }
-        T1[idx] = s1;
-        T2[idx] = s2;
+        T1[idx] = s1 * NLOG2E;
+        T2[idx] = s2 * NLOG2E;
     }
     for (int k = tid; k < K; k += NT) {
         const float hb = J.hb[k];
         float s = fabsf(hb);
         for (int q = 0; q < LW * LW; ++q) s += fabsf(W[k * LW * LW + q]);
-        hbs[k] = hb;
-        // table entries: <= LW-1 roundings; pre-activation: LW more
-        dAh[k] = gamma_f32(2 * LW + 2) * s * 1.001f;
+        hbs[k] = hb * NLOG2E;
+        // bound on |a_f32 - a| (table sums: <= LW-1 roundings, scaling 1, the
+        // pre-activation sum LW + 1 more)
+        dApre[k] = gamma_f32(2 * LW + 3) * s * 1.001f;
+        // band of the float32 test u(1 + 2^z) - 1: that error (ln 2 |dz| = |da|),
+        // 2 ulp of exp2, the fma and the float conversion of u
+        dAh[k] = dApre[k] + 0x1p-20f;
+        dAh[K + k] = s;  // S_k = |h_b| + sum |W_k|, kept for the free-energy bound
     }
     if (tid == 0) {
         const float vb = J.vb[0];
         float s = fabsf(vb);
         for (int q = 0; q < K * LW * LW; ++q) s += fabsf(W[q]);
-        sh_vb = vb;
-        sh_dAv = gamma_f32(K * LW + LW + 2) * s * 1.001f;
+        sh_vb = vb * NLOG2E;
+        sh_vb_raw = vb;
+        sh_dAv = gamma_f32(K * LW + LW + 3) * s * 1.001f + 0x1p-20f;
     }
 
     const uint32_t gid = J.chain_offset + (uint32_t)g;
@@ -235,29 +308,34 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
     for (int r = 0; r < nrounds; ++r) {
         const int Q = r * NT + tid;
         const bool active = Q < nq;
-        const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+        const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
         uint32_t nib = 0;
         if (active) {
-            const uint32_t w4 = ~*(const uint32_t*)(state + i * L + 4 * m);
+            const uint32_t w4 = ~*(const uint32_t*)(state + (i << lgL) + 4 * m);
             nib = ((w4 >> 7) & 1u) | ((w4 >> 14) & 2u) | ((w4 >> 21) & 4u) | ((w4 >> 28) & 8u);
         }
         store_nibble(vpl, RS, L, i, m, nib, active);
     }
-    ChainRec R;
-    double Bcur = 0.0;
     if (tid == 0) {
         R = *rec;
         sh_t0 = R.sweeps;
-        Bcur = R.reserved[0];
+        sh_Bcur = R.reserved[0];
     }
     __syncthreads();
     long long Ecur_d, Mcur;
     ising_em_bits(vpl, L, RS, (long long*)red, Ecur_d, Mcur);
     const double beta = 1.0 / J.T[g];
     const uint32_t t0 = (uint32_t)sh_t0;
-    const float vb = sh_vb, dAv = sh_dAv;
-    float dAh_sum = 0.f;
-    for (int k = 0; k < K; ++k) dAh_sum += dAh[k];
+    const float vb = sh_vb, dAv = sh_dAv, vb_raw = sh_vb_raw;
+    // rigorous bound of the float32 free energy, per site: pre-activation errors,
+    // exp2/log2 and product roundings, sum of the max terms
+    float dAsum = 0.f, Ssum = 0.f;
+    for (int k = 0; k < K; ++k) {
+        dAsum += dApre[k];
+        Ssum += dAh[K + k];
+    }
+    const double Bsite = (double)dAsum + (double)(K + 2) * 0x1p-20 + (double)(K + 2) * 0x1p-24 * 1.5 * (double)Ssum;
+    const double Bchain = Bsite * (double)L * (double)L;
 
     int cur = 0;
     int nre = 0, nre_mh = 0;
@@ -265,143 +343,196 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
         const uint32_t t = t0 + (uint32_t)it;
         int src = cur;
         for (int sub = 0; sub < J.gibbs_k; ++sub) {
-            int dst = (src + 1) % 3;
-            if (dst == cur) dst = (dst + 1) % 3;
+            int dst = src == 2 ? 0 : src + 1;
+            if (dst == cur) dst = dst == 2 ? 0 : dst + 1;
             const uint32_t* vs = vpl + src * PL;
             uint32_t* vd = vpl + dst * PL;
             const uint32_t tagh = STREAM_HID | ((uint32_t)sub << 8);
             const uint32_t tagv = STREAM_VIS | ((uint32_t)sub << 8);
+            if (tid == 0) sh_qn = 0;
+            __syncthreads();
             // ---- hidden pass: h ~ P(h | v)
             for (int r = 0; r < nrounds; ++r) {
                 const int Q = r * NT + tid;
                 const bool active = Q < nq;
-                const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+                const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
                 const int j0 = 4 * m;
-                uint32_t win[LW];
+                uint32_t off[LW][4];
 #pragma unroll
                 for (int a = 0; a < LW; ++a) {
-                    int ia = i + a;
-                    if (ia >= L) ia -= L;
-                    win[a] = window32(vs + ia * RS, j0);
+                    const uint32_t w = window32(vs + ((i + a) & Lm) * RS, j0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
                 }
+                const uint32_t q0 = (uint32_t)((i << lgL) + j0) >> 2;
+                const uint32_t qstride = (uint32_t)(L * L) >> 2;
+#pragma unroll KU
                 for (int k = 0; k < K; ++k) {
-                    const float* Tk = T1 + k * LW * NP;
-                    const float hk = hbs[k];
-                    float acc[4] = {hk, hk, hk, hk};
-#pragma unroll
-                    for (int a = 0; a < LW; ++a)
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((win[a] >> s) & (NP - 1))];
-                    const u32x4 rn = philox10((uint32_t)(((k * L + i) * L + j0) >> 2), t, gid, tagh, k0, k1);
-                    uint32_t nib = 0;
+                    float acc[4];
+                    table_sums<LW>(T1 + k * LW * NP, off, hbs[k], acc);
+                    const u32x4 rn = philox10(q0 + (uint32_t)k * qstride, t, gid, tagh, k0, k1);
+                    uint32_t nib = 0, nearb = 0;
                     const float dk = dAh[k];
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        bool near;
-                        const uint32_t x = word_of(rn, s);
-                        bool on = bernoulli_fast(acc[s], x, dk, near);
-                        if (near && active) {
-                            on = bernoulli_exact(preact_h_exact<LW>(W, hk, vs, RS, L, k, i, j0 + s), x);
-                            ++nre;
-                        }
-                        nib |= (uint32_t)on << s;
+                        const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                        const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
+                        nib |= (uint32_t)(tt < 0.0f) << s;
+                        nearb |= (uint32_t)(fabsf(tt) <= dk) << s;
+                    }
+                    if (nearb != 0 && active) {
+                        for (int s = 0; s < 4; ++s)
+                            if ((nearb >> s) & 1) {
+                                const int pos = atomicAdd(&sh_qn, 1);
+                                if (pos < QCAP) nearq[pos] = ((uint32_t)((k << lgL) + i) << lgL) + (uint32_t)(j0 + s);
+                            }
                     }
                     store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
                 }
             }
             __syncthreads();
+            {
+                // FP64 decisions of the queued hidden units (exact-mode rescan on overflow)
+                const int n = sh_qn;
+                if (n > 0) {
+                    if (n <= QCAP) {
+                        for (int e = tid; e < n; e += NT) {
+                            const uint32_t q = nearq[e];
+                            const int k = (int)(q >> (2 * lgL)), i = (int)(q >> lgL) & Lm, j = (int)q & Lm;
+                            const u32x4 rn = philox10(q >> 2, t, gid, tagh, k0, k1);
+                            const bool on =
+                                bernoulli_exact(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3));
+                            put_bit(hpl + k * PL, RS, L, i, j, on);
+                        }
+                    } else {
+                        for (int q = tid; q < (K << (2 * lgL)); q += NT) {
+                            const int k = q >> (2 * lgL), i = (q >> lgL) & Lm, j = q & Lm;
+                            const u32x4 rn = philox10((uint32_t)q >> 2, t, gid, tagh, k0, k1);
+                            const bool on =
+                                bernoulli_exact(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3));
+                            put_bit(hpl + k * PL, RS, L, i, j, on);
+                        }
+                    }
+                    nre += tid == 0 ? n : 0;
+                    __syncthreads();
+                    if (tid == 0) sh_qn = 0;
+                    __syncthreads();
+                }
+            }
             // ---- visible pass: v' ~ P(v | h)
             for (int r = 0; r < nrounds; ++r) {
                 const int Q = r * NT + tid;
                 const bool active = Q < nq;
-                const int x = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+                const int x = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
                 const int y0 = 4 * m;
-                int jst = y0 - (LW - 1);
-                if (jst < 0) jst += L;
+                const int jst = (y0 - (LW - 1)) & Lm;
                 float acc[4] = {vb, vb, vb, vb};
+#pragma unroll KU
                 for (int k = 0; k < K; ++k) {
                     const uint32_t* hk = hpl + k * PL;
-                    const float* Tk = T2 + k * LW * NP;
+                    uint32_t off[LW][4];
 #pragma unroll
                     for (int a = 0; a < LW; ++a) {
-                        int xa = x - a;
-                        if (xa < 0) xa += L;
-                        const uint32_t w = window32(hk + xa * RS, jst);
+                        const uint32_t w = window32(hk + ((x - a) & Lm) * RS, jst);
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((w >> s) & (NP - 1))];
+                        for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
                     }
+                    float part[4];
+                    table_sums<LW>(T2 + k * LW * NP, off, 0.f, part);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[s] += part[s];
                 }
-                const u32x4 rn = philox10((uint32_t)((x * L + y0) >> 2), t, gid, tagv, k0, k1);
-                uint32_t nib = 0;
+                const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
+                uint32_t nib = 0, nearb = 0;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    bool near;
-                    const uint32_t xr = word_of(rn, s);
-                    bool on = bernoulli_fast(acc[s], xr, dAv, near);
-                    if (near && active) {
-                        on = bernoulli_exact(preact_v_exact<LW>(W, vb, hpl, PL, RS, L, K, x, y0 + s), xr);
-                        ++nre;
-                    }
-                    nib |= (uint32_t)on << s;
+                    const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                    const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
+                    nib |= (uint32_t)(tt < 0.0f) << s;
+                    nearb |= (uint32_t)(fabsf(tt) <= dAv) << s;
+                }
+                if (nearb != 0 && active) {
+                    for (int s = 0; s < 4; ++s)
+                        if ((nearb >> s) & 1) {
+                            const int pos = atomicAdd(&sh_qn, 1);
+                            if (pos < QCAP) nearq[pos] = ((uint32_t)x << lgL) + (uint32_t)(y0 + s);
+                        }
                 }
                 store_nibble(vd, RS, L, x, m, nib, active);
             }
             __syncthreads();
+            {
+                const int n = sh_qn;
+                if (n > 0) {
+                    if (n <= QCAP) {
+                        for (int e = tid; e < n; e += NT) {
+                            const uint32_t q = nearq[e];
+                            const int x = (int)(q >> lgL), y = (int)q & Lm;
+                            const u32x4 rn = philox10(q >> 2, t, gid, tagv, k0, k1);
+                            const bool on =
+                                bernoulli_exact(preact_v_exact<LW>(W, vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3));
+                            put_bit(vd, RS, L, x, y, on);
+                        }
+                    } else {
+                        for (int q = tid; q < (1 << (2 * lgL)); q += NT) {
+                            const int x = q >> lgL, y = q & Lm;
+                            const u32x4 rn = philox10((uint32_t)q >> 2, t, gid, tagv, k0, k1);
+                            const bool on =
+                                bernoulli_exact(preact_v_exact<LW>(W, vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3));
+                            put_bit(vd, RS, L, x, y, on);
+                        }
+                    }
+                    nre += tid == 0 ? n : 0;
+                    __syncthreads();
+                }
+            }
             src = dst;
         }
         // ---- F(x') with its error bound, E(x'), M(x')
         const uint32_t* vp = vpl + src * PL;
         double Floc = 0.0;
-        float bnd = 0.f;
         for (int r = 0; r < nrounds; ++r) {
             const int Q = r * NT + tid;
             const bool active = Q < nq;
-            const int i = active ? Q / qpr : 0, m = active ? Q - (Q / qpr) * qpr : 0;
+            const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
             const int j0 = 4 * m;
-            uint32_t win[LW];
+            uint32_t off[LW][4];
 #pragma unroll
             for (int a = 0; a < LW; ++a) {
-                int ia = i + a;
-                if (ia >= L) ia -= L;
-                win[a] = window32(vp + ia * RS, j0);
+                const uint32_t w = window32(vp + ((i + a) & Lm) * RS, j0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
             }
-            float msum[4] = {0.f, 0.f, 0.f, 0.f}, prod[4] = {1.f, 1.f, 1.f, 1.f}, asum[4] = {0.f, 0.f, 0.f, 0.f};
+            // softplus(a) / ln 2 = max(z', 0) + log2(1 + 2^{-|z'|}) with z' = -z = a log2(e)
+            float msum[4] = {0.f, 0.f, 0.f, 0.f}, prod[4] = {1.f, 1.f, 1.f, 1.f};
+#pragma unroll KU
             for (int k = 0; k < K; ++k) {
-                const float* Tk = T1 + k * LW * NP;
-                const float hk = hbs[k];
-                float acc[4] = {hk, hk, hk, hk};
-#pragma unroll
-                for (int a = 0; a < LW; ++a)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[s] += Tk[a * NP + ((win[a] >> s) & (NP - 1))];
+                float acc[4];
+                table_sums<LW>(T1 + k * LW * NP, off, hbs[k], acc);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float av = fabsf(acc[s]);
-                    msum[s] += fmaxf(acc[s], 0.f);
-                    prod[s] *= 1.0f + __builtin_amdgcn_exp2f(-av * 1.44269504088896341f);
-                    asum[s] += av;
+                    msum[s] += fmaxf(-acc[s], 0.f);
+                    prod[s] = fmaf(prod[s], __builtin_amdgcn_exp2f(-fabsf(acc[s])), prod[s]);
                 }
             }
             if (active) {
+                float fs = 0.f;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float ss = msum[s] + __builtin_amdgcn_logf(prod[s]) * 0.693147180559945309f;
-                    Floc -= (double)ss;
-                    bnd += (float)(K + 2) * (0x1p-24f * (asum[s] + fabsf(ss)) + 0x1p-19f);
-                }
+                for (int s = 0; s < 4; ++s) fs += msum[s] + __builtin_amdgcn_logf(prod[s]);
+                Floc -= (double)fs * 0.693147180559945309;
             }
         }
         const double Fsp = block_sum(Floc, red);
-        const double Bp = block_sum((double)bnd, red) + (double)dAh_sum * L * L;
+        const double Bp = Bchain + 1e-13 * fabs(Fsp);
         long long Ep, Mp;
         ising_em_bits(vp, L, RS, (long long*)red, Ep, Mp);
         const long long ones = (Mp + (long long)L * L) / 2;
-        const double Fp = Fsp - (double)vb * (double)ones;
+        const double Fp = Fsp - (double)vb_raw * (double)ones;
         double lu = 0.0;
         if (tid == 0) {
             const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
             lu = log(mh_uniform(J.seed, t, gid));
-            const double band = Bp + Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
+            const double band = Bp + sh_Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
             sh_flag = (fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2;
         }
         __syncthreads();
@@ -409,14 +540,14 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
         double Fnew = Fp, Bnew = Bp, Fold = 0.0;
         if (flag == 2) {
             // inside the float32 band: decide with FP64 free energies of both states
-            Fnew = free_energy_exact<LW>(W, hbs, vb, vp, RS, L, K, red);
-            Fold = free_energy_exact<LW>(W, hbs, vb, vpl + cur * PL, RS, L, K, red);
+            Fnew = free_energy_exact<LW>(W, J.hb, vb_raw, vp, RS, L, K, red);
+            Fold = free_energy_exact<LW>(W, J.hb, vb_raw, vpl + cur * PL, RS, L, K, red);
             Bnew = 0.0;
             if (tid == 0) {
                 const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fnew - Fold);
                 sh_flag = lu < logr ? 1 : 0;
                 R.F = Fold;
-                Bcur = 0.0;
+                sh_Bcur = 0.0;
                 ++nre_mh;
             }
             __syncthreads();
@@ -425,7 +556,7 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
         if (tid == 0) {
             if (flag) {
                 R.F = Fnew;
-                Bcur = Bnew;
+                sh_Bcur = Bnew;
                 R.E = Ep;
                 R.n_acc += 1;
             }
@@ -450,17 +581,17 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
     for (int r = 0; r < nrounds; ++r) {
         const int Q = r * NT + tid;
         if (Q < nq) {
-            const int i = Q / qpr, m = Q - (Q / qpr) * qpr;
+            const int i = Q >> lgq, m = Q & ((L >> 2) - 1);
             const uint32_t nib = quad_bits(vpl + cur * PL, RS, L, i, m);
             const uint32_t up = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
             const uint32_t dn = ((~nib) & 1u) | (((~nib) & 2u) << 7) | (((~nib) & 4u) << 14) | (((~nib) & 8u) << 21);
-            *(uint32_t*)(state + i * L + 4 * m) = up | (dn * 0xFFu);
+            *(uint32_t*)(state + (i << lgL) + 4 * m) = up | (dn * 0xFFu);
         }
     }
     const int tot = block_sum(nre, (int*)red);
     if (tid == 0) {
         R.n_recheck += tot + nre_mh;
-        R.reserved[0] = Bcur;
+        R.reserved[0] = sh_Bcur;
         *rec = R;
     }
 }
@@ -471,7 +602,7 @@ __global__ __launch_bounds__(NT) void sweep_ising_kernel(SweepLaunch P)
 bool ising_fast_supported(int K, int LW, int L)
 {
     if (LW < 1 || LW > 6 || LW > L || K < 1 || K > 64) return false;
-    if (!(L == 8 || L == 16 || (L % 32 == 0 && L <= 256))) return false;
+    if (!(L == 8 || L == 16 || L == 32 || L == 64 || L == 128 || L == 256)) return false;
     return ising_fast_lds_bytes(K, LW, L) <= 160 * 1024;
 }
 
@@ -486,25 +617,25 @@ int ising_fast_threads(int L)
 size_t ising_fast_lds_bytes(int K, int LW, int L)
 {
     const size_t tsz = (size_t)K * LW * ((size_t)1 << LW);
-    size_t o = ((2 * tsz + 2 * (size_t)K) * 4 + 15) & ~(size_t)15;
+    size_t o = ((2 * tsz + 4 * (size_t)K) * 4 + 15) & ~(size_t)15;
     o += 64 * 8;
     const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
     o += (3 + (size_t)K) * (size_t)L * RS * 4;
     return o;
 }
 
-template <int LW>
-static hipError_t launch_lw(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
+template <int KT, int LW>
+static hipError_t launch_klw(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
 {
     switch (nt) {
     case 64:
-        hipLaunchKernelGGL((sweep_ising_kernel<LW, 64>), dim3(n_blocks), dim3(64), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 64>), dim3(n_blocks), dim3(64), lds, s, P);
         break;
     case 256:
-        hipLaunchKernelGGL((sweep_ising_kernel<LW, 256>), dim3(n_blocks), dim3(256), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 256>), dim3(n_blocks), dim3(256), lds, s, P);
         break;
     case 512:
-        hipLaunchKernelGGL((sweep_ising_kernel<LW, 512>), dim3(n_blocks), dim3(512), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 512>), dim3(n_blocks), dim3(512), lds, s, P);
         break;
     default:
         return hipErrorInvalidValue;
@@ -514,14 +645,18 @@ static hipError_t launch_lw(const SweepLaunch& P, int n_blocks, size_t lds, int 
 
 hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int n_blocks, size_t lds, int nt, hipStream_t s)
 {
-    (void)K;
+    // channel counts of the configured workloads get unrolled instances
+    if (K == 8 && LW == 5) return launch_klw<8, 5>(P, n_blocks, lds, nt, s);
+    if (K == 8 && LW == 3) return launch_klw<8, 3>(P, n_blocks, lds, nt, s);
+    if (K == 4 && LW == 3) return launch_klw<4, 3>(P, n_blocks, lds, nt, s);
+    if (K == 2 && LW == 2) return launch_klw<2, 2>(P, n_blocks, lds, nt, s);
     switch (LW) {
-    case 1: return launch_lw<1>(P, n_blocks, lds, nt, s);
-    case 2: return launch_lw<2>(P, n_blocks, lds, nt, s);
-    case 3: return launch_lw<3>(P, n_blocks, lds, nt, s);
-    case 4: return launch_lw<4>(P, n_blocks, lds, nt, s);
-    case 5: return launch_lw<5>(P, n_blocks, lds, nt, s);
-    case 6: return launch_lw<6>(P, n_blocks, lds, nt, s);
+    case 1: return launch_klw<0, 1>(P, n_blocks, lds, nt, s);
+    case 2: return launch_klw<0, 2>(P, n_blocks, lds, nt, s);
+    case 3: return launch_klw<0, 3>(P, n_blocks, lds, nt, s);
+    case 4: return launch_klw<0, 4>(P, n_blocks, lds, nt, s);
+    case 5: return launch_klw<0, 5>(P, n_blocks, lds, nt, s);
+    case 6: return launch_klw<0, 6>(P, n_blocks, lds, nt, s);
     default: return hipErrorInvalidValue;
     }
 }
