@@ -180,6 +180,16 @@ CRBM_API crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32
                       float* dW, float* dhbias, float* dvbias, void* workspace, size_t workspace_bytes,
                       void* stream);
 
+/* Tile choice of the bit-packed Ising sweep for jobs with this (L, K, Lw):
+ * `rows` lattice rows x 4 columns per lane (1, 2 or 4) and `threads` per
+ * workgroup (64, 256, 512 or 1024).  Process-wide; applies to jobs created after the
+ * call.  Results do not depend on the choice (random numbers are indexed by
+ * unit, sweep and chain), only speed does.  Host only. */
+CRBM_API crbm_status crbm_set_tuning(int32_t L, int32_t K, int32_t Lw, int32_t rows, int32_t threads);
+
+/* Forget every tile choice (defaults apply again). Host only. */
+CRBM_API crbm_status crbm_clear_tuning(void);
+
 /* Message of the last error on the calling thread ("" if none). */
 CRBM_API const char* crbm_last_error(void);
 

@@ -45,7 +45,8 @@ assert STATS_DTYPE.itemsize == 160
 
 EXPORTS = ["crbm_workspace_size", "crbm_init", "crbm_propose_accept", "crbm_propose_accept_many",
            "crbm_read_stats", "crbm_sweeps_done", "crbm_destroy", "crbm_free_energy", "target_energy",
-           "crbm_grad_workspace_size", "crbm_grad", "crbm_last_error", "crbm_version"]
+           "crbm_grad_workspace_size", "crbm_grad", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
+           "crbm_version"]
 
 _lib = None
 
@@ -73,6 +74,10 @@ def load(path: str = LIB_PATH):
     L.crbm_grad_workspace_size.argtypes = [P(crbm_params), ct.c_int32]
     L.crbm_grad_workspace_size.restype = ct.c_size_t
     L.crbm_grad.argtypes = [P(crbm_params), vp, ct.c_int32, ct.c_int32, vp, vp, vp, vp, vp, ct.c_size_t, vp]
+    L.crbm_set_tuning.argtypes = [ct.c_int32] * 5
+    L.crbm_set_tuning.restype = ct.c_int
+    L.crbm_clear_tuning.argtypes = []
+    L.crbm_clear_tuning.restype = ct.c_int
     L.crbm_last_error.restype = ct.c_char_p
     L.crbm_version.restype = ct.c_char_p
     for name in ("crbm_init", "crbm_propose_accept", "crbm_propose_accept_many", "crbm_read_stats",
@@ -134,6 +139,14 @@ def crbm_grad_workspace_size(params, B) -> int:
 
 def crbm_grad(params, x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, ws_ptr, ws_bytes, stream):
     check(load().crbm_grad(ct.byref(params), x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, ws_ptr, ws_bytes, stream))
+
+
+def crbm_set_tuning(L, K, Lw, rows, threads):
+    check(load().crbm_set_tuning(int(L), int(K), int(Lw), int(rows), int(threads)))
+
+
+def crbm_clear_tuning():
+    check(load().crbm_clear_tuning())
 
 
 def crbm_last_error() -> str:

@@ -10,8 +10,20 @@ import numpy as np
 import torch
 
 from . import _lib as C
+from . import autotune as _autotune
 
 ISING, KITAEV = C.CRBM_ISING, C.CRBM_KITAEV
+
+# tile choices measured by the autotuner for this device (speed only)
+_autotune.apply()
+
+
+def set_tuning(L: int, K: int, Lw: int, rows: int, threads: int):
+    C.crbm_set_tuning(L, K, Lw, rows, threads)
+
+
+def clear_tuning():
+    C.crbm_clear_tuning()
 
 
 def _stream_ptr(stream=None) -> int:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -57,8 +58,28 @@ enum Kernel { K_GENERIC = 0, K_ISING_FAST = 1 };
 struct Plan {
     int kernel;
     int nt;
+    int rows;  // rows per lane block (bit-packed kernel)
     size_t lds;
 };
+
+// process-wide tile choices for the bit-packed kernel, set by the autotuner
+struct TuneEntry {
+    int L, K, Lw, rows, nt;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+bool lookup_tuning(int L, int K, int Lw, int* rows, int* nt)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry& t : g_tune)
+        if (t.L == L && t.K == K && t.Lw == Lw) {
+            *rows = t.rows;
+            *nt = t.nt;
+            return true;
+        }
+    return false;
+}
 
 crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
 {
@@ -77,6 +98,8 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->target == CRBM_ISING && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
         pl.nt = ising_fast_threads(d->L);
+        pl.rows = ising_fast_rows(d->L);
+        lookup_tuning(d->L, p->K, p->Lw, &pl.rows, &pl.nt);
         pl.lds = ising_fast_lds_bytes(p->K, p->Lw, d->L);
     } else {
         pl.kernel = K_GENERIC;
@@ -118,6 +141,7 @@ crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
         const Plan& pb = ctxs[b]->plan;
         if (pa.kernel != pb.kernel) return pa.kernel < pb.kernel;
         if (pa.nt != pb.nt) return pa.nt < pb.nt;
+        if (pa.rows != pb.rows) return pa.rows < pb.rows;
         if (pa.kernel == K_ISING_FAST && ctxs[a]->params.K != ctxs[b]->params.K) return ctxs[a]->params.K < ctxs[b]->params.K;
         if (pa.kernel == K_ISING_FAST && ctxs[a]->params.Lw != ctxs[b]->params.Lw)
             return ctxs[a]->params.Lw < ctxs[b]->params.Lw;
@@ -136,7 +160,7 @@ crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
         int nj = 0;
         while (i < order.size() && nj < MAX_JOBS_PER_LAUNCH) {
             const crbm_ctx* c = ctxs[order[i]];
-            if (c->plan.kernel != c0->plan.kernel || c->plan.nt != c0->plan.nt) break;
+            if (c->plan.kernel != c0->plan.kernel || c->plan.nt != c0->plan.nt || c->plan.rows != c0->plan.rows) break;
             if (c0->plan.kernel == K_ISING_FAST && (c->params.K != c0->params.K || c->params.Lw != c0->params.Lw)) break;
             P.jobs[nj] = c->job_dev;
             P.block_begin[nj] = blocks;
@@ -149,7 +173,7 @@ crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
         P.n_jobs = nj;
         hipError_t e;
         if (c0->plan.kernel == K_ISING_FAST)
-            e = launch_ising_fast(P, c0->params.K, c0->params.Lw, blocks, lds, c0->plan.nt, s);
+            e = launch_ising_fast(P, c0->params.K, c0->params.Lw, c0->plan.rows, blocks, lds, c0->plan.nt, s);
         else
             e = launch_generic(P, blocks, lds, c0->plan.nt, s);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
@@ -354,6 +378,33 @@ crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int
     hipError_t e = launch_grad(params->W, params->hbias, params->K, params->C, params->Lw, x, B, L, gF,
                                (double*)workspace, dW, dhbias, dvbias, (hipStream_t)stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_grad launch");
+}
+
+crbm_status crbm_set_tuning(int32_t L, int32_t K, int32_t Lw, int32_t rows, int32_t threads)
+{
+    if (!(L == 8 || L == 16 || L == 32 || L == 64 || L == 128 || L == 256))
+        return fail(CRBM_EINVAL, "tuning applies to L in {8,...,256} powers of two (got %d)", L);
+    if (K < 1 || K > 64 || Lw < 1 || Lw > 6 || Lw > L) return fail(CRBM_EINVAL, "invalid K=%d Lw=%d", K, Lw);
+    if (rows != 1 && rows != 2 && rows != 4) return fail(CRBM_EINVAL, "rows=%d must be 1, 2 or 4", rows);
+    if (4 * rows > L) return fail(CRBM_EINVAL, "rows=%d too many for L=%d", rows, L);
+    if (threads != 64 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(CRBM_EINVAL, "threads=%d not in {64,256,512,1024}", threads);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TuneEntry& t : g_tune)
+        if (t.L == L && t.K == K && t.Lw == Lw) {
+            t.rows = rows;
+            t.nt = threads;
+            return CRBM_OK;
+        }
+    g_tune.push_back({L, K, Lw, rows, threads});
+    return CRBM_OK;
+}
+
+crbm_status crbm_clear_tuning(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return CRBM_OK;
 }
 
 const char* crbm_last_error(void) { return g_err.c_str(); }

@@ -8,7 +8,9 @@ namespace crbm {
 
 bool ising_fast_supported(int K, int LW, int L);
 int ising_fast_threads(int L);
+int ising_fast_rows(int L);
 size_t ising_fast_lds_bytes(int K, int LW, int L);
-hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int n_blocks, size_t lds, int nt, hipStream_t s);
+hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int BH, int n_blocks, size_t lds, int nt,
+                             hipStream_t s);
 
 }  // namespace crbm

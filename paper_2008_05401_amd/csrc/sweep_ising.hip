@@ -213,16 +213,59 @@ __device__ __forceinline__ void table_sums(const float* __restrict__ T, const ui
     }
 }
 
+// acc[s] = bias + sum_a T[a NP + idx[b + a][s]] (visible-to-hidden, rows below)
+template <int LW, int R>
+__device__ __forceinline__ void table_sums_fwd(const float* __restrict__ T, const uint32_t (&idx)[R][4], int b,
+                                               float bias, float (&acc)[4])
+{
+    constexpr int NP = 1 << LW;
+    float v[LW][4];
+#pragma unroll
+    for (int a = 0; a < LW; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[a][s] = T[a * NP + idx[b + a][s]];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float t = v[0][s];
+#pragma unroll
+        for (int a = 1; a + 1 < LW; a += 2) t += v[a][s] + v[a + 1][s];
+        if ((LW & 1) == 0) t += v[LW - 1][s];
+        acc[s] = bias + t;
+    }
+}
+
+// part[s] = sum_a T[a NP + idx[b - a + LW - 1][s]] (hidden-to-visible, rows above)
+template <int LW, int R>
+__device__ __forceinline__ void table_sums_adj(const float* __restrict__ T, const uint32_t (&idx)[R][4], int b,
+                                               float (&part)[4])
+{
+    constexpr int NP = 1 << LW;
+    float v[LW][4];
+#pragma unroll
+    for (int a = 0; a < LW; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[a][s] = T[a * NP + idx[b - a + LW - 1][s]];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float t = v[0][s];
+#pragma unroll
+        for (int a = 1; a + 1 < LW; a += 2) t += v[a][s] + v[a + 1][s];
+        if ((LW & 1) == 0) t += v[LW - 1][s];
+        part[s] = t;
+    }
+}
+
 }  // namespace
 
 // KT > 0: the number of hidden channels is a compile-time constant (loops over
 // channels unrolled, table offsets become instruction immediates); KT == 0:
 // runtime K.  L is a power of two in {8, ..., 256}.
-template <int KT, int LW, int NT>
+template <int KT, int LW, int NT, int BH>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sweep_ising_kernel(SweepLaunch P)
 {
     constexpr int NP = 1 << LW;
-    constexpr int KU = KT > 0 ? KT : 1;  // unroll factor of the channel loops
+    // unroll factor of the channel loops (unrolling with rows > 1 runs out of registers)
+    constexpr int KU = (KT > 0 && BH == 1) ? KT : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     int jb = 0;
     while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
@@ -237,8 +280,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     const int RS = (L >= 32 ? (L >> 5) : 1) + 1;
     const int PL = L * RS;
     const int lgq = lgL - 2;  // quads per row = L/4
-    const int nq = (L * L) >> 2;
+    const int nq = (L * L) >> 2;          // quads of 4 sites (state load/store)
+    const int nb = nq / BH;               // blocks of BH x 4 sites (the passes)
     const int nrounds = (nq + NT - 1) / NT;
+    const int nbrounds = (nb + NT - 1) / NT;
     const int tid = threadIdx.x;
     const int tsz = K * LW * NP;
 
@@ -351,43 +396,48 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             const uint32_t tagv = STREAM_VIS | ((uint32_t)sub << 8);
             if (tid == 0) sh_qn = 0;
             __syncthreads();
-            // ---- hidden pass: h ~ P(h | v)
-            for (int r = 0; r < nrounds; ++r) {
+            // ---- hidden pass: h ~ P(h | v); a lane owns BH rows x 4 columns
+            for (int r = 0; r < nbrounds; ++r) {
                 const int Q = r * NT + tid;
-                const bool active = Q < nq;
-                const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+                const bool active = Q < nb;
+                const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
                 const int j0 = 4 * m;
-                uint32_t off[LW][4];
+                uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-                for (int a = 0; a < LW; ++a) {
-                    const uint32_t w = window32(vs + ((i + a) & Lm) * RS, j0);
+                for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                    const uint32_t w = window32(vs + ((i0 + r2) & Lm) * RS, j0);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
+                    for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
                 }
-                const uint32_t q0 = (uint32_t)((i << lgL) + j0) >> 2;
-                const uint32_t qstride = (uint32_t)(L * L) >> 2;
 #pragma unroll KU
                 for (int k = 0; k < K; ++k) {
-                    float acc[4];
-                    table_sums<LW>(T1 + k * LW * NP, off, hbs[k], acc);
-                    const u32x4 rn = philox10(q0 + (uint32_t)k * qstride, t, gid, tagh, k0, k1);
-                    uint32_t nib = 0, nearb = 0;
                     const float dk = dAh[k];
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
-                        const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
-                        nib |= (uint32_t)(tt < 0.0f) << s;
-                        nearb |= (uint32_t)(fabsf(tt) <= dk) << s;
+                    for (int b = 0; b < BH; ++b) {
+                        const int i = i0 + b;
+                        float acc[4];
+                        table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], acc);
+                        const u32x4 rn = philox10((uint32_t)((((k << lgL) + i) << lgL) + j0) >> 2, t, gid, tagh, k0, k1);
+                        uint32_t nib = 0, nearb = 0;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                            const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
+                            nib |= (uint32_t)(tt < 0.0f) << s;
+                            nearb |= (uint32_t)(fabsf(tt) <= dk) << s;
+                        }
+                        if (nearb != 0 && active) {
+                            for (int s = 0; s < 4; ++s)
+                                if ((nearb >> s) & 1) {
+                                    const int pos = atomicAdd(&sh_qn, 1);
+                                    if (pos < QCAP)
+                                        nearq[pos] = ((uint32_t)((k << lgL) + i) << lgL) + (uint32_t)(j0 + s);
+                                }
+                        }
+                        store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
                     }
-                    if (nearb != 0 && active) {
-                        for (int s = 0; s < 4; ++s)
-                            if ((nearb >> s) & 1) {
-                                const int pos = atomicAdd(&sh_qn, 1);
-                                if (pos < QCAP) nearq[pos] = ((uint32_t)((k << lgL) + i) << lgL) + (uint32_t)(j0 + s);
-                            }
-                    }
-                    store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
+                    // keep the scheduler from hoisting the next channel's table reads
+                    if (BH > 1) __builtin_amdgcn_sched_barrier(0);
                 }
             }
             __syncthreads();
@@ -420,45 +470,57 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                 }
             }
             // ---- visible pass: v' ~ P(v | h)
-            for (int r = 0; r < nrounds; ++r) {
+            for (int r = 0; r < nbrounds; ++r) {
                 const int Q = r * NT + tid;
-                const bool active = Q < nq;
-                const int x = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+                const bool active = Q < nb;
+                const int x0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
                 const int y0 = 4 * m;
                 const int jst = (y0 - (LW - 1)) & Lm;
-                float acc[4] = {vb, vb, vb, vb};
+                float acc[BH][4];
+#pragma unroll
+                for (int b = 0; b < BH; ++b)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[b][s] = vb;
 #pragma unroll KU
                 for (int k = 0; k < K; ++k) {
                     const uint32_t* hk = hpl + k * PL;
-                    uint32_t off[LW][4];
+                    uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-                    for (int a = 0; a < LW; ++a) {
-                        const uint32_t w = window32(hk + ((x - a) & Lm) * RS, jst);
+                    for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                        const uint32_t w = window32(hk + ((x0 - (LW - 1) + r2) & Lm) * RS, jst);
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
+                        for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
                     }
-                    float part[4];
-                    table_sums<LW>(T2 + k * LW * NP, off, 0.f, part);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[s] += part[s];
-                }
-                const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
-                uint32_t nib = 0, nearb = 0;
+                    for (int b = 0; b < BH; ++b) {
+                        float part[4];
+                        table_sums_adj<LW>(T2 + k * LW * NP, idx, b, part);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
-                    const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
-                    nib |= (uint32_t)(tt < 0.0f) << s;
-                    nearb |= (uint32_t)(fabsf(tt) <= dAv) << s;
+                        for (int s = 0; s < 4; ++s) acc[b][s] += part[s];
+                    }
+                    if (BH > 1) __builtin_amdgcn_sched_barrier(0);
                 }
-                if (nearb != 0 && active) {
-                    for (int s = 0; s < 4; ++s)
-                        if ((nearb >> s) & 1) {
-                            const int pos = atomicAdd(&sh_qn, 1);
-                            if (pos < QCAP) nearq[pos] = ((uint32_t)x << lgL) + (uint32_t)(y0 + s);
-                        }
+#pragma unroll
+                for (int b = 0; b < BH; ++b) {
+                    const int x = x0 + b;
+                    const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
+                    uint32_t nib = 0, nearb = 0;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                        const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[b][s]), u - 1.0f);
+                        nib |= (uint32_t)(tt < 0.0f) << s;
+                        nearb |= (uint32_t)(fabsf(tt) <= dAv) << s;
+                    }
+                    if (nearb != 0 && active) {
+                        for (int s = 0; s < 4; ++s)
+                            if ((nearb >> s) & 1) {
+                                const int pos = atomicAdd(&sh_qn, 1);
+                                if (pos < QCAP) nearq[pos] = ((uint32_t)x << lgL) + (uint32_t)(y0 + s);
+                            }
+                    }
+                    store_nibble(vd, RS, L, x, m, nib, active);
                 }
-                store_nibble(vd, RS, L, x, m, nib, active);
             }
             __syncthreads();
             {
@@ -491,34 +553,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         // ---- F(x') with its error bound, E(x'), M(x')
         const uint32_t* vp = vpl + src * PL;
         double Floc = 0.0;
-        for (int r = 0; r < nrounds; ++r) {
+        for (int r = 0; r < nbrounds; ++r) {
             const int Q = r * NT + tid;
-            const bool active = Q < nq;
-            const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+            const bool active = Q < nb;
+            const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
             const int j0 = 4 * m;
-            uint32_t off[LW][4];
+            uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-            for (int a = 0; a < LW; ++a) {
-                const uint32_t w = window32(vp + ((i + a) & Lm) * RS, j0);
+            for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                const uint32_t w = window32(vp + ((i0 + r2) & Lm) * RS, j0);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) off[a][s] = (uint32_t)(a * NP) + ((w >> s) & (NP - 1));
+                for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
             }
             // softplus(a) / ln 2 = max(z', 0) + log2(1 + 2^{-|z'|}) with z' = -z = a log2(e)
-            float msum[4] = {0.f, 0.f, 0.f, 0.f}, prod[4] = {1.f, 1.f, 1.f, 1.f};
-#pragma unroll KU
-            for (int k = 0; k < K; ++k) {
-                float acc[4];
-                table_sums<LW>(T1 + k * LW * NP, off, hbs[k], acc);
+            float msum[BH][4], prod[BH][4];
+#pragma unroll
+            for (int b = 0; b < BH; ++b)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    msum[s] += fmaxf(-acc[s], 0.f);
-                    prod[s] = fmaf(prod[s], __builtin_amdgcn_exp2f(-fabsf(acc[s])), prod[s]);
+                    msum[b][s] = 0.f;
+                    prod[b][s] = 1.f;
                 }
+#pragma unroll KU
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int b = 0; b < BH; ++b) {
+                    float acc[4];
+                    table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], acc);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        msum[b][s] += fmaxf(-acc[s], 0.f);
+                        prod[b][s] = fmaf(prod[b][s], __builtin_amdgcn_exp2f(-fabsf(acc[s])), prod[b][s]);
+                    }
+                }
+                if (BH > 1) __builtin_amdgcn_sched_barrier(0);
             }
             if (active) {
                 float fs = 0.f;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) fs += msum[s] + __builtin_amdgcn_logf(prod[s]);
+                for (int b = 0; b < BH; ++b)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) fs += msum[b][s] + __builtin_amdgcn_logf(prod[b][s]);
                 Floc -= (double)fs * 0.693147180559945309;
             }
         }
@@ -606,11 +681,13 @@ bool ising_fast_supported(int K, int LW, int L)
     return ising_fast_lds_bytes(K, LW, L) <= 160 * 1024;
 }
 
+int ising_fast_rows(int L) { return L >= 32 ? 4 : 1; }
+
 int ising_fast_threads(int L)
 {
-    const int nq = L * L / 4;
-    if (nq <= 64) return 64;
-    if (nq <= 1024) return 256;
+    const int nb = L * L / (4 * ising_fast_rows(L));
+    if (nb <= 64) return 64;
+    if (nb <= 1024) return 256;
     return 512;
 }
 
@@ -624,18 +701,21 @@ size_t ising_fast_lds_bytes(int K, int LW, int L)
     return o;
 }
 
-template <int KT, int LW>
-static hipError_t launch_klw(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
+template <int KT, int LW, int BH>
+static hipError_t launch_klwb(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
 {
     switch (nt) {
     case 64:
-        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 64>), dim3(n_blocks), dim3(64), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 64, BH>), dim3(n_blocks), dim3(64), lds, s, P);
         break;
     case 256:
-        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 256>), dim3(n_blocks), dim3(256), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 256, BH>), dim3(n_blocks), dim3(256), lds, s, P);
         break;
     case 512:
-        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 512>), dim3(n_blocks), dim3(512), lds, s, P);
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 512, BH>), dim3(n_blocks), dim3(512), lds, s, P);
+        break;
+    case 1024:
+        hipLaunchKernelGGL((sweep_ising_kernel<KT, LW, 1024, BH>), dim3(n_blocks), dim3(1024), lds, s, P);
         break;
     default:
         return hipErrorInvalidValue;
@@ -643,20 +723,29 @@ static hipError_t launch_klw(const SweepLaunch& P, int n_blocks, size_t lds, int
     return hipGetLastError();
 }
 
-hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int n_blocks, size_t lds, int nt, hipStream_t s)
+template <int KT, int LW>
+static hipError_t launch_klw(const SweepLaunch& P, int BH, int n_blocks, size_t lds, int nt, hipStream_t s)
+{
+    if (BH == 4) return launch_klwb<KT, LW, 4>(P, n_blocks, lds, nt, s);
+    if (BH == 2) return launch_klwb<KT, LW, 2>(P, n_blocks, lds, nt, s);
+    return launch_klwb<KT, LW, 1>(P, n_blocks, lds, nt, s);
+}
+
+hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int BH, int n_blocks, size_t lds, int nt,
+                             hipStream_t s)
 {
     // channel counts of the configured workloads get unrolled instances
-    if (K == 8 && LW == 5) return launch_klw<8, 5>(P, n_blocks, lds, nt, s);
-    if (K == 8 && LW == 3) return launch_klw<8, 3>(P, n_blocks, lds, nt, s);
-    if (K == 4 && LW == 3) return launch_klw<4, 3>(P, n_blocks, lds, nt, s);
-    if (K == 2 && LW == 2) return launch_klw<2, 2>(P, n_blocks, lds, nt, s);
+    if (K == 8 && LW == 5) return launch_klw<8, 5>(P, BH, n_blocks, lds, nt, s);
+    if (K == 8 && LW == 3) return launch_klw<8, 3>(P, BH, n_blocks, lds, nt, s);
+    if (K == 4 && LW == 3) return launch_klw<4, 3>(P, BH, n_blocks, lds, nt, s);
+    if (K == 2 && LW == 2) return launch_klw<2, 2>(P, BH, n_blocks, lds, nt, s);
     switch (LW) {
-    case 1: return launch_klw<0, 1>(P, n_blocks, lds, nt, s);
-    case 2: return launch_klw<0, 2>(P, n_blocks, lds, nt, s);
-    case 3: return launch_klw<0, 3>(P, n_blocks, lds, nt, s);
-    case 4: return launch_klw<0, 4>(P, n_blocks, lds, nt, s);
-    case 5: return launch_klw<0, 5>(P, n_blocks, lds, nt, s);
-    case 6: return launch_klw<0, 6>(P, n_blocks, lds, nt, s);
+    case 1: return launch_klw<0, 1>(P, BH, n_blocks, lds, nt, s);
+    case 2: return launch_klw<0, 2>(P, BH, n_blocks, lds, nt, s);
+    case 3: return launch_klw<0, 3>(P, BH, n_blocks, lds, nt, s);
+    case 4: return launch_klw<0, 4>(P, BH, n_blocks, lds, nt, s);
+    case 5: return launch_klw<0, 5>(P, BH, n_blocks, lds, nt, s);
+    case 6: return launch_klw<0, 6>(P, BH, n_blocks, lds, nt, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -120,3 +120,35 @@ def test_resume_is_bitwise(api):
     sa, sc = a.stats(), c.stats()
     for name in ("sweeps", "n_acc", "sumE", "sumE2", "sumM", "E"):
         assert np.array_equal(sa[name], sc[name])
+
+
+@pytest.mark.parametrize("L", [32, 64])
+def test_tile_shapes_give_identical_chains(orc, api, L):
+    # every (rows, threads) tile choice yields the same chains (doubles as a race check)
+    from paper_2008_05401_amd import autotune
+    f = WL.random_filters_with_bias(8, 1, 5, 0.06, 0.05, seed=4)
+    T = np.linspace(1.8, 3.0, 12)
+    ref = None
+    try:
+        for rows, nt in autotune.candidates(L):
+            api.set_tuning(L, 8, 5, rows, nt)
+            job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=13, burnin=2)
+            job.run(5)
+            job.run(4)
+            st = job.stats()
+            got = (job.state.cpu().numpy(), st)
+            if ref is None:
+                ref = got
+                ch = orc.Chains(orc.CRBM(f.W, f.hbias, f.vbias), orc.ISING, L, T, seed=13, burnin=2)
+                ch.run(9)
+                assert np.array_equal(ref[0], ch.state)
+            else:
+                assert np.array_equal(got[0], ref[0]), (rows, nt)
+                for name in ("n_acc", "E", "sumE", "sumE2", "sumM", "sumAbsM", "sumM2"):
+                    assert np.array_equal(st[name], ref[1][name]), (rows, nt, name)
+                # F: float32 terms grouped per lane block, so equal only within the two bounds
+                tol = st["reserved"][:, 0] + ref[1]["reserved"][:, 0] + 1e-11 * np.abs(st["F"])
+                assert np.all(np.abs(st["F"] - ref[1]["F"]) <= tol), (rows, nt)
+    finally:
+        api.clear_tuning()
+        autotune.apply()
