@@ -62,6 +62,45 @@ def cpu_baseline(f, T, L, seed, seconds=15.0):
     }
 
 
+def served(n_jobs, rate, warmup_s, n_sweeps, plain_jobs):
+    """Served Ising jobs: Poisson arrivals, L uniform in {16,...,256}, T ~ U[1.8,2.8],
+    64-1024 chains (log-uniform), 8 5x5 filters ~N(0,0.05) per job, 16 GiB budget."""
+    import torch
+
+    from paper_2008_05401_amd import serve, workloads as WL
+    total = n_jobs + int(rate * warmup_s)
+    specs = WL.served_job_stream(total, rate_per_s=rate, n_sweeps=n_sweeps, seed=0)
+    srv = serve.Server(budget_bytes=16 << 30, max_block=10)
+    t0 = time.perf_counter()
+    res = srv.run(specs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    summ = serve.latency_summary(res, warmup_s=warmup_s)
+    measured = [r for r in res if r.arrival_s >= warmup_s]
+    span = max(r.done_s for r in measured) - min(r.arrival_s for r in measured)
+    by_id = {sp.job_id: sp for sp in specs}
+    site_sweeps = sum(by_id[r.job_id].n_chains * by_id[r.job_id].L ** 2 * n_sweeps for r in measured)
+    # plain form: each chain alone, one launch per chain, jobs one after another
+    sample = [sp for sp in specs[-plain_jobs:]]
+    t1 = time.perf_counter()
+    for sp in sample:
+        serve.run_plain(sp)
+    plain_t = (time.perf_counter() - t1) / len(sample)
+    plain_ss = sum(sp.n_chains * sp.L ** 2 * n_sweeps for sp in sample) / (plain_t * len(sample))
+    return {
+        "workload": f"Poisson {rate:.0f} jobs/s, L in {{16,32,64,128,256}}, T~U[1.8,2.8], 64-1024 chains "
+                    f"log-uniform, K=8 5x5 filters, {n_sweeps} sweeps per job, 16 GiB budget",
+        "jobs_measured": summ["jobs"], "warmup_s": warmup_s,
+        "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+        "jobs_per_s": summ["jobs"] / span, "site_sweeps_per_s": site_sweeps / span, "wall_s": wall,
+        "plain_one_chain_per_launch": {
+            "service_ms_per_job": plain_t * 1e3, "max_jobs_per_s": 1.0 / plain_t,
+            "site_sweeps_per_s": plain_ss, "sample_jobs": len(sample),
+            "note": "jobs run one after another; at the offered load the plain form's queue grows without bound "
+                    "whenever max_jobs_per_s is below the arrival rate"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +110,12 @@ def main():
     ap.add_argument("--chains", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-served", action="store_true", help="skip the served-jobs measurement")
+    ap.add_argument("--served-jobs", type=int, default=2000)
+    ap.add_argument("--served-rate", type=float, default=200.0)
+    ap.add_argument("--served-warmup", type=float, default=5.0)
+    ap.add_argument("--served-sweeps", type=int, default=20)
+    ap.add_argument("--plain-jobs", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (scale for HBM counters)")
     args = ap.parse_args()
@@ -170,6 +215,10 @@ def main():
             "hbm_frac": 2.0 * n * L * L / avg_launch_s / 1e9 / PEAK_HBM_GBS,
         },
     }
+    if not args.no_served:
+        del job
+        out["served"] = served(args.served_jobs, args.served_rate, args.served_warmup, args.served_sweeps,
+                               args.plain_jobs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, T, L, seed, args.cpu_seconds)
     print(json.dumps(out), flush=True)
