@@ -101,6 +101,73 @@ def served(n_jobs, rate, warmup_s, n_sweeps, plain_jobs):
     }
 
 
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def kitaev(sweeps6=20, sweeps12=2):
+    """Kitaev honeycomb, J = (1,1,1), periodic, u on 3 L^2 bonds, CRBM K=8 3x3 ~ N(0,0.1):
+    L=6 with 256 chains and L=12 with 128 chains, T log-uniform in [0.005, 0.05]."""
+    from paper_2008_05401_amd import api, workloads as WL
+    out = {}
+    for L, n, sw in ((6, 256, sweeps6), (12, 128, sweeps12)):
+        f = WL.random_filters(8, 3, 3, 0.1, seed=0)
+        job = api.Job(api.CRBMParams.from_filters(f), api.KITAEV, L, WL.kitaev_temperatures(n), seed=0)
+        job.run(1)
+        ms = _timed(lambda: job.run(sw)) / sw
+        st = job.stats()
+        N = L * L
+        out[f"L{L}_chains{n}"] = {
+            "ms_per_sweep": ms, "mh_steps_per_s": n / (ms * 1e-3),
+            "eigen_flops_per_sweep": n * (4.0 / 3.0) * N ** 3,
+            "acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
+    return out
+
+
+def training_and_transfer(epochs=20, lr=1e-2):
+    """Gradient of F at B=1024 Ising states (L=16, T=2.3), a short Alg. 1 training
+    run, and sampling at L=128 with 2048 chains using the trained filters."""
+    import torch
+
+    from paper_2008_05401_amd import api, train
+    L, T = 16, 2.3
+    x, E, acc0 = train.exact_ising_samples(L, T, 1024, sweeps=1000, seed=0)
+    f0 = train.workloads.alg1_init_filters(8, 5, seed=0)
+    p0 = api.CRBMParams.from_filters(f0)
+    g = torch.randn(1024, device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+    api.grad(p0, x, g)
+    grad_ms = _timed(lambda: api.grad(p0, x, g), reps=20)
+    fwd_ms = _timed(lambda: api.free_energy(p0, x), reps=20)
+    z1 = torch.zeros(1, device="cuda")
+    loss0 = train.full_loss(x, E, T, p0.W, p0.hbias, z1)
+    t0 = time.perf_counter()
+    r = train.train(x, E, T, epochs=epochs, batch=20, ub=200, lr=lr, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss1 = train.full_loss(x, E, T, r.W, r.hbias, r.vbias)
+    job = api.Job(api.CRBMParams(r.W, r.hbias, r.vbias), api.ISING, 128, np.full(2048, T), seed=1)
+    job.run(5)
+    sw = 20
+    ms = _timed(lambda: job.run(sw))
+    st = job.stats()
+    return {
+        "grad_ms_B1024_L16": grad_ms, "free_energy_ms_B1024_L16": fwd_ms,
+        "exact_sample_acceptance": acc0, "train_epochs": epochs, "train_steps": r.steps, "train_s": train_s,
+        "adam_lr": lr, "minibatch": 20, "replay_update": 200,
+        "loss_init": loss0, "loss_trained": loss1,
+        "transfer_L128_chains2048_site_sweeps_per_s": 2048 * 128 * 128 * sw / (ms * 1e-3),
+        "transfer_acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +178,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true", help="skip the served-jobs measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the Kitaev and training measurements")
     ap.add_argument("--served-jobs", type=int, default=2000)
     ap.add_argument("--served-rate", type=float, default=200.0)
     ap.add_argument("--served-warmup", type=float, default=5.0)
@@ -215,6 +283,9 @@ def main():
             "hbm_frac": 2.0 * n * L * L / avg_launch_s / 1e9 / PEAK_HBM_GBS,
         },
     }
+    if not args.no_extra:
+        out["kitaev"] = kitaev()
+        out["training"] = training_and_transfer()
     if not args.no_served:
         del job
         out["served"] = served(args.served_jobs, args.served_rate, args.served_warmup, args.served_sweeps,

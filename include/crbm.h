@@ -69,7 +69,11 @@ typedef enum {
     CRBM_EUNSUPPORTED = -4 /* valid but not supported by this build (e.g. LDS too small) */
 } crbm_status;
 
-typedef enum { CRBM_ISING = 0, CRBM_KITAEV = 1 } crbm_target;
+/* CRBM_GIBBS: no target; every proposal is accepted, so the chain is the plain
+ * block-Gibbs chain of the CRBM (App. B) -- the sampler of the replay buffer of
+ * Alg. 1 and the "uncorrected" RBM of App. B.  Needs C = 1; the Ising
+ * observables of the states are still accumulated. */
+typedef enum { CRBM_ISING = 0, CRBM_KITAEV = 1, CRBM_GIBBS = 2 } crbm_target;
 
 /* CRBM parameters theta = (W, hbias, vbias); all device, float32.
  * K in [1, 64], C in {1, 3}, Lw in [1, 8] and Lw <= L. */

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "crbm_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-ISING, KITAEV = 0, 1
+ISING, KITAEV, GIBBS = 0, 1, 2
 ST_INIT, ST_HID, ST_VIS, ST_MH = 0, 1, 2, 3
 
 

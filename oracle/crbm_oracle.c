@@ -374,7 +374,7 @@ typedef struct {
 } orc_chain;
 
 typedef struct {
-    int32_t target; /* 0 Ising, 1 Kitaev */
+    int32_t target; /* 0 Ising, 1 Kitaev, 2 plain Gibbs chain (no MH) */
     int32_t L, n_chains, gibbs_k, burnin;
     uint32_t g0;
     uint64_t seed;
@@ -397,7 +397,7 @@ ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const do
             memset(R, 0, sizeof *R);
             spins_to_visible(s, C, L, v);
             R->F = free_energy_v(P, v, L, a);
-            if (D->target == 0) {
+            if (D->target != 1) {
                 R->E = orc_ising_energy(s, L);
             } else {
                 R->S = orc_kitaev_S(s, C, L, D->J, 1.0 / T[g], NULL, &R->Ef, &R->Cf);
@@ -445,7 +445,7 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                 double logr;
                 int64_t Ep = 0;
                 double Sp = 0, Efp = 0, Cfp = 0;
-                if (D->target == 0) {
+                if (D->target != 1) {
                     Ep = orc_ising_energy(sp, L);
                     logr = -beta * D->J[0] * (double)(Ep - R->E) + (Fp - R->F);
                 } else {
@@ -453,20 +453,21 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                     logr = (Sp - R->S) + (Fp - R->F);
                 }
                 const double lu = log(orc_mh_uniform(D->seed, t, gid));
-                if (fabs(logr - lu) < 1e-6) ++mt;
-                const int acc = lu < logr;
+                /* target 2: plain Gibbs chain of the CRBM, every proposal accepted */
+                if (D->target != 2 && fabs(logr - lu) < 1e-6) ++mt;
+                const int acc = D->target == 2 ? 1 : (lu < logr);
                 if (accept_log) accept_log[(size_t)g * n_sweeps + it] = (uint8_t)acc;
                 if (acc) {
                     memcpy(s, sp, (size_t)nv);
                     R->F = Fp;
-                    if (D->target == 0) R->E = Ep;
+                    if (D->target != 1) R->E = Ep;
                     else { R->S = Sp; R->Ef = Efp; R->Cf = Cfp; }
                     R->n_acc += 1;
                 }
                 R->sweeps += 1;
                 if ((int64_t)t >= (int64_t)D->burnin) {
                     R->n_meas += 1;
-                    if (D->target == 0) {
+                    if (D->target != 1) {
                         const int64_t m = orc_magnetization(s, L);
                         R->sumE += R->E;
                         R->sumE2 += R->E * R->E;

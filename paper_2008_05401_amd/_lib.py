@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcrbm.so")
 
 CRBM_OK, CRBM_EINVAL, CRBM_EBUDGET, CRBM_EHIP, CRBM_EUNSUPPORTED = 0, -1, -2, -3, -4
-CRBM_ISING, CRBM_KITAEV = 0, 1
+CRBM_ISING, CRBM_KITAEV, CRBM_GIBBS = 0, 1, 2
 
 
 class CRBMError(RuntimeError):

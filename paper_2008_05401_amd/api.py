@@ -12,7 +12,7 @@ import torch
 from . import _lib as C
 from . import autotune as _autotune
 
-ISING, KITAEV = C.CRBM_ISING, C.CRBM_KITAEV
+ISING, KITAEV, GIBBS = C.CRBM_ISING, C.CRBM_KITAEV, C.CRBM_GIBBS
 
 # tile choices measured by the autotuner for this device (speed only)
 _autotune.apply()

@@ -86,16 +86,17 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     crbm_status st = check_params(p);
     if (st != CRBM_OK) return st;
     if (!d) return fail(CRBM_EINVAL, "desc is NULL");
-    if (d->target != CRBM_ISING && d->target != CRBM_KITAEV) return fail(CRBM_EINVAL, "unknown target %d", d->target);
+    if (d->target != CRBM_ISING && d->target != CRBM_KITAEV && d->target != CRBM_GIBBS)
+        return fail(CRBM_EINVAL, "unknown target %d", d->target);
     if (d->L < 1 || d->L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", d->L);
     if (p->Lw > d->L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", p->Lw, d->L);
     if (d->n_chains < 1) return fail(CRBM_EINVAL, "n_chains=%d must be >= 1", d->n_chains);
     if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
-    if (d->target == CRBM_ISING && p->C != 1) return fail(CRBM_EINVAL, "Ising needs C=1 (got %d)", p->C);
+    if (d->target != CRBM_KITAEV && p->C != 1) return fail(CRBM_EINVAL, "Ising and Gibbs-only jobs need C=1 (got %d)", p->C);
     if (d->target == CRBM_KITAEV && d->L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", d->L);
     Plan pl{};
-    if (d->target == CRBM_ISING && ising_fast_supported(p->K, p->Lw, d->L)) {
+    if (d->target != CRBM_KITAEV && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
         pl.nt = ising_fast_threads(d->L);
         pl.rows = ising_fast_rows(d->L);

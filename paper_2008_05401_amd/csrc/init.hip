@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     const double F = free_energy_block(Ws, hbs, vbs, v, K, C, LW, L, red);
     long long E = 0, M = 0;
     KitaevOut ko{0.0, 0.0, 0.0};
-    if (J.target == 0) {
+    if (J.target != 1) {
         ising_em_block(v, L, (long long*)red, E, M);
     } else {
         const int N = LL;

@@ -108,7 +108,8 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 
     const double T = J.T[g];
     const double beta = 1.0 / T;
-    const bool ising = J.target == 0;
+    const bool ising = J.target != 1;      // Ising or Gibbs-only (C = 1)
+    const bool gibbs_only = J.target == 2;
 
     // ---------------------------------------------------------------- sweeps
     __shared__ long long sh_t0;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
         if (tid == 0) {
             const double logr = ising ? (-beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F)) : ((ko.S - R.S) + (Fp - R.F));
             const double lu = log(mh_uniform(J.seed, t, gid));
-            const int acc = lu < logr;
+            const int acc = gibbs_only ? 1 : (lu < logr);
             sh_acc = acc;
             if (acc) {
                 R.F = Fp;

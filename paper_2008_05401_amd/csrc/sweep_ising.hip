@@ -608,7 +608,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
             lu = log(mh_uniform(J.seed, t, gid));
             const double band = Bp + sh_Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
-            sh_flag = (fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2;
+            sh_flag = J.target == 2 ? 1 : ((fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2);
         }
         __syncthreads();
         int flag = sh_flag;

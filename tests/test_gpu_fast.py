@@ -152,3 +152,18 @@ def test_tile_shapes_give_identical_chains(orc, api, L):
     finally:
         api.clear_tuning()
         autotune.apply()
+
+
+@pytest.mark.parametrize("L,K,Lw", [(16, 8, 5), (5, 3, 2), (64, 8, 5)])
+def test_gibbs_only_target(orc, api, L, K, Lw):
+    f = WL.random_filters_with_bias(K, 1, Lw, 0.3, 0.2, seed=L)
+    T = np.full(8, 2.0)
+    job = api.Job(api.CRBMParams.from_filters(f), api.GIBBS, L, T, seed=21, burnin=1)
+    ch = orc.Chains(orc.CRBM(f.W, f.hbias, f.vbias), orc.GIBBS, L, T, seed=21, burnin=1)
+    job.run(7)
+    ch.run(7)
+    st = job.stats()
+    assert np.array_equal(job.state.cpu().numpy(), ch.state)
+    assert np.all(st["n_acc"] == 7)
+    for name in ("E", "sumE", "sumM2"):
+        assert np.array_equal(st[name], ch.rec[name])

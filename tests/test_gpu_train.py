@@ -1,0 +1,66 @@
+"""The hand-written backward behind torch.autograd (CRBMFreeEnergy) against the
+oracle's gradient of the paper's loss, and a short training run of Alg. 1
+followed by transfer to a larger lattice."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2008_05401_amd import workloads as WL  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_05401_amd import api, train
+    return api, train
+
+
+def test_autograd_loss_gradient_matches_oracle(mods, orc):
+    api, _ = mods
+    L, T = 16, 2.3
+    f = WL.random_filters_with_bias(8, 1, 5, 0.05, 0.1, seed=2)
+    x = WL.random_states(40, 1, L, seed=3)
+    E = orc.target(orc.ISING, x).astype(np.float64)
+    W = torch.tensor(f.W, device="cuda", requires_grad=True)
+    hb = torch.tensor(f.hbias, device="cuda", requires_grad=True)
+    vb = torch.tensor(f.vbias, device="cuda", requires_grad=True)
+    xt = torch.from_numpy(x).cuda()
+    F = api.crbm_free_energy_fn(xt, W, hb, vb)
+    diff = torch.from_numpy(E).cuda() / T - F
+    loss = ((diff - diff.mean()) ** 2).mean()
+    loss.backward()
+    # oracle: dloss/dtheta = sum_n g_n dF_n/dtheta with g_n = -2 (diff_n - C) / M
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    Fo = orc.free_energy(m, x)
+    d = E / T - Fo
+    g = -2.0 * (d - d.mean()) / len(d)
+    dWo, dhbo, dvbo = orc.grad(m, x, g)
+    for got, ref in ((W.grad, dWo), (hb.grad, dhbo), (vb.grad, dvbo)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-7
+
+
+def test_training_reduces_loss_and_transfers(mods):
+    api, train = mods
+    L, T = 16, 2.3
+    x, E, acc = train.exact_ising_samples(L, T, 256, sweeps=200, seed=0)
+    assert acc > 0.9
+    # learning rate 2e-2 (the paper's 1e-3 needs thousands of steps to reach |W| ~ 2.7)
+    r = train.train(x, E, T, epochs=10, batch=20, ub=64, lr=2e-2, seed=0)
+    f0 = WL.alg1_init_filters(8, 5, seed=0)
+    W0 = torch.tensor(f0.W, device="cuda")
+    z = torch.zeros(8, device="cuda")
+    l0 = train.full_loss(x, E, T, W0, z, torch.zeros(1, device="cuda"))
+    l1 = train.full_loss(x, E, T, r.W, r.hbias, r.vbias)
+    assert l1 < 0.5 * l0, (l0, l1)
+    # transfer: the trained filters propose better L=64 moves than the initial ones
+    def acceptance(W, hb, vb):
+        job = api.Job(api.CRBMParams(W, hb, vb), api.ISING, 64, np.full(64, T), seed=5)
+        job.run(30)
+        st = job.stats()
+        return st["n_acc"].sum() / st["sweeps"].sum()
+    assert acceptance(r.W, r.hbias, r.vbias) >= acceptance(W0, z, torch.zeros(1, device="cuda"))

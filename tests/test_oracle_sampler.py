@@ -128,3 +128,26 @@ def test_run_is_resumable_bitwise(orc):
     b.run(18)
     assert np.array_equal(a.state, b.state)
     assert a.rec.tobytes() == b.rec.tobytes()
+
+
+def test_gibbs_only_chain_keeps_crbm_distribution(orc):
+    # target 2: every proposal accepted, i.e. the plain Gibbs chain of App. B, whose
+    # stationary law is P_RBM ~ exp(-F); starting from exact P_RBM samples it stays there
+    L = 3
+    f = WL.random_filters_with_bias(2, 1, 2, 0.8, 0.4, seed=12)
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    states = X.all_states(L)[:, None]
+    F = orc.free_energy(m, states)
+    p = np.exp(-(F - F.min()))
+    p /= p.sum()
+    n = 20000
+    s0 = states[np.random.default_rng(4).choice(len(p), size=n, p=p)].copy()
+    ch = orc.Chains(m, orc.GIBBS, L, np.full(n, 2.0), seed=6, state=s0)
+    ch.run(6)
+    assert np.all(ch.rec["n_acc"] == 6)
+    counts = np.bincount(X.state_index(ch.state[:, 0]), minlength=2 ** (L * L)).astype(np.float64)
+    chi2, dof, pv = X.chi2_pvalue(counts, p)
+    assert pv > 1e-4, (chi2, dof)
+    # and it is not the Ising distribution
+    _, _, p_ising = X.chi2_pvalue(counts, X.boltzmann_weights(X.all_states(L), 2.0))
+    assert p_ising < 1e-8
