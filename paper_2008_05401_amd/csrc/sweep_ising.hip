@@ -255,17 +255,69 @@ __device__ __forceinline__ void table_sums_adj(const float* __restrict__ T, cons
     }
 }
 
+// e[s] = bias * prod_a T[a NP + idx[b + a][s]] (tree order)
+template <int LW, int R>
+__device__ __forceinline__ void table_prods_fwd(const float* __restrict__ T, const uint32_t (&idx)[R][4], int b,
+                                                float bias, float (&e)[4])
+{
+    constexpr int NP = 1 << LW;
+    float v[LW][4];
+#pragma unroll
+    for (int a = 0; a < LW; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[a][s] = T[a * NP + idx[b + a][s]];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float t = v[0][s];
+#pragma unroll
+        for (int a = 1; a + 1 < LW; a += 2) t *= v[a][s] * v[a + 1][s];
+        if ((LW & 1) == 0) t *= v[LW - 1][s];
+        e[s] = bias * t;
+    }
+}
+
+// part[s] = prod_a T[a NP + idx[b - a + LW - 1][s]]
+template <int LW, int R>
+__device__ __forceinline__ void table_prods_adj(const float* __restrict__ T, const uint32_t (&idx)[R][4], int b,
+                                                float (&part)[4])
+{
+    constexpr int NP = 1 << LW;
+    float v[LW][4];
+#pragma unroll
+    for (int a = 0; a < LW; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[a][s] = T[a * NP + idx[b - a + LW - 1][s]];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float t = v[0][s];
+#pragma unroll
+        for (int a = 1; a + 1 < LW; a += 2) t *= v[a][s] * v[a + 1][s];
+        if ((LW & 1) == 0) t *= v[LW - 1][s];
+        part[s] = t;
+    }
+}
+
+template <bool B>
+struct flag_c {
+    static constexpr bool value = B;
+};
+
 }  // namespace
 
 // KT > 0: the number of hidden channels is a compile-time constant (loops over
 // channels unrolled, table offsets become instruction immediates); KT == 0:
 // runtime K.  L is a power of two in {8, ..., 256}.
+// filter loop unroll: full for a compile-time K with one row per lane (more spills)
+template <int KT, int BH>
+struct KUnroll {
+    static constexpr int value = (KT > 0 && BH == 1) ? KT : 1;
+};
+
 template <int KT, int LW, int NT, int BH>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sweep_ising_kernel(SweepLaunch P)
 {
     constexpr int NP = 1 << LW;
     // unroll factor of the channel loops (unrolling with rows > 1 runs out of registers)
-    constexpr int KU = (KT > 0 && BH == 1) ? KT : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     int jb = 0;
     while (jb + 1 < P.n_jobs && (int)blockIdx.x >= P.block_begin[jb + 1]) ++jb;
@@ -287,15 +339,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     const int tid = threadIdx.x;
     const int tsz = K * LW * NP;
 
+    // tables: additive mode T1, T2 (exp2 domain); product mode E1 = e^{-s},
+    // E2 = e^{-s} of the reversed rows, E1p = e^{+s}
     float* T1 = (float*)smem;
     float* T2 = T1 + tsz;
-    float* hbs = T2 + tsz;
-    float* dAh = hbs + K;      // [2K]: Bernoulli bands, then S_k
-    float* dApre = dAh + 2 * K;
-    double* red = (double*)(smem + (((size_t)(2 * tsz + 4 * K) * 4 + 15) & ~(size_t)15));
+    float* E1p = T2 + tsz;
+    float* hbs = E1p + tsz;    // additive: -h_b log2(e)
+    float* dAh = hbs + K;      // Bernoulli band per channel
+    float* Sk = dAh + K;       // S_k = |h_b| + sum |W_k|
+    float* dApre = Sk + K;     // bound on |a_f32 - a| (additive mode)
+    float* ehbm = dApre + K;   // e^{-h_b}
+    float* ehbp = ehbm + K;    // e^{+h_b}
+    double* red = (double*)(smem + (((size_t)(3 * tsz + 6 * K) * 4 + 15) & ~(size_t)15));
     uint32_t* vpl = (uint32_t*)(red + 64);
     uint32_t* hpl = vpl + 3 * PL;
-    __shared__ float sh_vb, sh_dAv, sh_vb_raw;
+    __shared__ float sh_vb, sh_dAv, sh_vb_raw, sh_evbm, sh_Sv;
     __shared__ long long sh_t0;
     __shared__ int sh_flag;
     // units whose float32 Bernoulli test fell inside its error band
@@ -307,33 +365,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
 
     const float* __restrict__ W = J.W;
     constexpr float NLOG2E = -1.44269504088896341f;
-    // subset-sum tables of every filter row, scaled by -log2(e) so that the
-    // passes produce z = -a log2(e) directly (exp2(z) = e^{-a})
-    for (int idx = tid; idx < tsz; idx += NT) {
-        const int p = idx & (NP - 1), ka = idx >> LW;
-        const float* wr = W + ka * LW;  // (k * LW + a) * LW with C = 1
-        float s1 = 0.f, s2 = 0.f;
-#pragma unroll
-        for (int b = 0; b < LW; ++b) {
-            const float w = wr[b];
-            if ((p >> b) & 1) s1 += w;
-            if ((p >> (LW - 1 - b)) & 1) s2 += w;
-        }
-        T1[idx] = s1 * NLOG2E;
-        T2[idx] = s2 * NLOG2E;
-    }
     for (int k = tid; k < K; k += NT) {
         const float hb = J.hb[k];
         float s = fabsf(hb);
         for (int q = 0; q < LW * LW; ++q) s += fabsf(W[k * LW * LW + q]);
+        Sk[k] = s;
         hbs[k] = hb * NLOG2E;
-        // bound on |a_f32 - a| (table sums: <= LW-1 roundings, scaling 1, the
-        // pre-activation sum LW + 1 more)
-        dApre[k] = gamma_f32(2 * LW + 3) * s * 1.001f;
-        // band of the float32 test u(1 + 2^z) - 1: that error (ln 2 |dz| = |da|),
-        // 2 ulp of exp2, the fma and the float conversion of u
-        dAh[k] = dApre[k] + 0x1p-20f;
-        dAh[K + k] = s;  // S_k = |h_b| + sum |W_k|, kept for the free-energy bound
+        ehbm[k] = (float)exp(-(double)hb);
+        ehbp[k] = (float)exp((double)hb);
     }
     if (tid == 0) {
         const float vb = J.vb[0];
@@ -341,8 +380,61 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         for (int q = 0; q < K * LW * LW; ++q) s += fabsf(W[q]);
         sh_vb = vb * NLOG2E;
         sh_vb_raw = vb;
-        sh_dAv = gamma_f32(K * LW + LW + 3) * s * 1.001f + 0x1p-20f;
+        sh_evbm = (float)exp(-(double)vb);
+        sh_Sv = s;
     }
+    __syncthreads();
+    // Product mode when every partial product stays well inside the float32
+    // normal range: |log| of a hidden factor chain <= S_k, of a visible chain
+    // <= S_v, of the free-energy product over channels <= sum_k S_k + K.
+    float Smax = sh_Sv, Ssum = 0.f;
+    for (int k = 0; k < K; ++k) {
+        Smax = fmaxf(Smax, Sk[k]);
+        Ssum += Sk[k];
+    }
+    const bool mult = Smax < 80.f && Ssum + (float)K < 80.f;
+    // subset sums of every filter row (T1: taps in order, T2: reversed)
+    for (int idx = tid; idx < tsz; idx += NT) {
+        const int p = idx & (NP - 1), ka = idx >> LW;
+        const float* wr = W + ka * LW;  // (k * LW + a) * LW with C = 1
+        if (mult) {
+            double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < LW; ++b) {
+                const double w = (double)wr[b];
+                if ((p >> b) & 1) d1 += w;
+                if ((p >> (LW - 1 - b)) & 1) d2 += w;
+            }
+            T1[idx] = (float)exp(-d1);
+            T2[idx] = (float)exp(-d2);
+            E1p[idx] = (float)exp(d1);
+        } else {
+            float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int b = 0; b < LW; ++b) {
+                const float w = wr[b];
+                if ((p >> b) & 1) s1 += w;
+                if ((p >> (LW - 1 - b)) & 1) s2 += w;
+            }
+            T1[idx] = s1 * NLOG2E;
+            T2[idx] = s2 * NLOG2E;
+        }
+    }
+    for (int k = tid; k < K; k += NT) {
+        if (mult) {
+            // e^{-a} from LW+1 factors each rounded once, LW products
+            dApre[k] = 0.f;
+            dAh[k] = gamma_f32(2 * LW + 1) * 1.01f + 0x1p-22f;
+        } else {
+            // |a_f32 - a|: table sums <= LW-1 roundings, scaling 1, pre-activation LW + 1
+            dApre[k] = gamma_f32(2 * LW + 3) * Sk[k] * 1.001f;
+            // band of u(1 + 2^z) - 1: that error, 2 ulp of exp2, the fma, float u
+            dAh[k] = dApre[k] + 0x1p-20f;
+        }
+    }
+    if (tid == 0)
+        sh_dAv = mult ? gamma_f32(2 * K * LW + 1) * 1.01f + 0x1p-22f
+                      : gamma_f32(K * LW + LW + 3) * sh_Sv * 1.001f + 0x1p-20f;
 
     const uint32_t gid = J.chain_offset + (uint32_t)g;
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
@@ -371,15 +463,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     ising_em_bits(vpl, L, RS, (long long*)red, Ecur_d, Mcur);
     const double beta = 1.0 / J.T[g];
     const uint32_t t0 = (uint32_t)sh_t0;
-    const float vb = sh_vb, dAv = sh_dAv, vb_raw = sh_vb_raw;
-    // rigorous bound of the float32 free energy, per site: pre-activation errors,
-    // exp2/log2 and product roundings, sum of the max terms
-    float dAsum = 0.f, Ssum = 0.f;
-    for (int k = 0; k < K; ++k) {
-        dAsum += dApre[k];
-        Ssum += dAh[K + k];
-    }
-    const double Bsite = (double)dAsum + (double)(K + 2) * 0x1p-20 + (double)(K + 2) * 0x1p-24 * 1.5 * (double)Ssum;
+    const float vb = sh_vb, dAv = sh_dAv, vb_raw = sh_vb_raw, evbm = sh_evbm;
+    // rigorous bound of the float32 free energy per site
+    //   product mode: K factors (1 + e^{a_k}) with e^{a_k} from 2 LW + 1 roundings,
+    //   one rounding per product step; the FP64 log of the product is exact enough;
+    //   additive mode: pre-activation errors, exp2/log2 and product roundings, max terms
+    float dAsum = 0.f;
+    for (int k = 0; k < K; ++k) dAsum += dApre[k];
+    const double Bsite = mult ? (double)K * ((double)gamma_f32(2 * LW + 1) + 0x1p-24) * 1.02
+                              : (double)dAsum + (double)(K + 2) * 0x1p-20 +
+                                    (double)(K + 2) * 0x1p-24 * 1.5 * (double)Ssum;
     const double Bchain = Bsite * (double)L * (double)L;
 
     int cur = 0;
@@ -397,49 +490,63 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             if (tid == 0) sh_qn = 0;
             __syncthreads();
             // ---- hidden pass: h ~ P(h | v); a lane owns BH rows x 4 columns
-            for (int r = 0; r < nbrounds; ++r) {
-                const int Q = r * NT + tid;
-                const bool active = Q < nb;
-                const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
-                const int j0 = 4 * m;
-                uint32_t idx[BH + LW - 1][4];
+            auto hidden_pass = [&](auto MT) {
+                constexpr bool MULT = decltype(MT)::value;
+                for (int r = 0; r < nbrounds; ++r) {
+                    const int Q = r * NT + tid;
+                    const bool active = Q < nb;
+                    const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+                    const int j0 = 4 * m;
+                    uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-                for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
-                    const uint32_t w = window32(vs + ((i0 + r2) & Lm) * RS, j0);
+                    for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                        const uint32_t w = window32(vs + ((i0 + r2) & Lm) * RS, j0);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
-                }
-#pragma unroll KU
-                for (int k = 0; k < K; ++k) {
-                    const float dk = dAh[k];
-#pragma unroll
-                    for (int b = 0; b < BH; ++b) {
-                        const int i = i0 + b;
-                        float acc[4];
-                        table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], acc);
-                        const u32x4 rn = philox10((uint32_t)((((k << lgL) + i) << lgL) + j0) >> 2, t, gid, tagh, k0, k1);
-                        uint32_t nib = 0, nearb = 0;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
-                            const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[s]), u - 1.0f);
-                            nib |= (uint32_t)(tt < 0.0f) << s;
-                            nearb |= (uint32_t)(fabsf(tt) <= dk) << s;
-                        }
-                        if (nearb != 0 && active) {
-                            for (int s = 0; s < 4; ++s)
-                                if ((nearb >> s) & 1) {
-                                    const int pos = atomicAdd(&sh_qn, 1);
-                                    if (pos < QCAP)
-                                        nearq[pos] = ((uint32_t)((k << lgL) + i) << lgL) + (uint32_t)(j0 + s);
-                                }
-                        }
-                        store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
+                        for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
                     }
-                    // keep the scheduler from hoisting the next channel's table reads
-                    if (BH > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll KUnroll<KT, BH>::value
+                    for (int k = 0; k < K; ++k) {
+                        const float dk = dAh[k];
+#pragma unroll
+                        for (int b = 0; b < BH; ++b) {
+                            const int i = i0 + b;
+                            // e[s] = e^{-a} of the four units
+                            float e[4];
+                            if constexpr (MULT) {
+                                table_prods_fwd<LW>(T1 + k * LW * NP, idx, b, ehbm[k], e);
+                            } else {
+                                float z[4];
+                                table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], z);
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) e[s] = __builtin_amdgcn_exp2f(z[s]);
+                            }
+                            const u32x4 rn =
+                                philox10((uint32_t)((((k << lgL) + i) << lgL) + j0) >> 2, t, gid, tagh, k0, k1);
+                            uint32_t nib = 0, nearb = 0;
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                                const float tt = fmaf(u, e[s], u - 1.0f);
+                                nib |= (uint32_t)(tt < 0.0f) << s;
+                                nearb |= (uint32_t)(fabsf(tt) <= dk) << s;
+                            }
+                            if (nearb != 0 && active) {
+                                for (int s = 0; s < 4; ++s)
+                                    if ((nearb >> s) & 1) {
+                                        const int pos = atomicAdd(&sh_qn, 1);
+                                        if (pos < QCAP)
+                                            nearq[pos] = ((uint32_t)((k << lgL) + i) << lgL) + (uint32_t)(j0 + s);
+                                    }
+                            }
+                            store_nibble(hpl + k * PL, RS, L, i, m, nib, active);
+                        }
+                        // keep the scheduler from hoisting the next channel's table reads
+                        if (BH > 1) __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
-            }
+            };
+            if (mult) hidden_pass(flag_c<true>{});
+            else hidden_pass(flag_c<false>{});
             __syncthreads();
             {
                 // FP64 decisions of the queued hidden units (exact-mode rescan on overflow)
@@ -470,58 +577,71 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                 }
             }
             // ---- visible pass: v' ~ P(v | h)
-            for (int r = 0; r < nbrounds; ++r) {
-                const int Q = r * NT + tid;
-                const bool active = Q < nb;
-                const int x0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
-                const int y0 = 4 * m;
-                const int jst = (y0 - (LW - 1)) & Lm;
-                float acc[BH][4];
+            auto visible_pass = [&](auto MT) {
+                constexpr bool MULT = decltype(MT)::value;
+                for (int r = 0; r < nbrounds; ++r) {
+                    const int Q = r * NT + tid;
+                    const bool active = Q < nb;
+                    const int x0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+                    const int y0 = 4 * m;
+                    const int jst = (y0 - (LW - 1)) & Lm;
+                    // additive: z = -b log2(e); product: e = e^{-b}
+                    float acc[BH][4];
 #pragma unroll
-                for (int b = 0; b < BH; ++b)
+                    for (int b = 0; b < BH; ++b)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[b][s] = vb;
-#pragma unroll KU
-                for (int k = 0; k < K; ++k) {
-                    const uint32_t* hk = hpl + k * PL;
-                    uint32_t idx[BH + LW - 1][4];
+                        for (int s = 0; s < 4; ++s) acc[b][s] = MULT ? evbm : vb;
+#pragma unroll KUnroll<KT, BH>::value
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t* hk = hpl + k * PL;
+                        uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-                    for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
-                        const uint32_t w = window32(hk + ((x0 - (LW - 1) + r2) & Lm) * RS, jst);
+                        for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                            const uint32_t w = window32(hk + ((x0 - (LW - 1) + r2) & Lm) * RS, jst);
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
+                            for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
+                        }
+#pragma unroll
+                        for (int b = 0; b < BH; ++b) {
+                            float part[4];
+                            if constexpr (MULT) {
+                                table_prods_adj<LW>(T2 + k * LW * NP, idx, b, part);
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) acc[b][s] *= part[s];
+                            } else {
+                                table_sums_adj<LW>(T2 + k * LW * NP, idx, b, part);
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) acc[b][s] += part[s];
+                            }
+                        }
+                        if (BH > 1) __builtin_amdgcn_sched_barrier(0);
                     }
 #pragma unroll
                     for (int b = 0; b < BH; ++b) {
-                        float part[4];
-                        table_sums_adj<LW>(T2 + k * LW * NP, idx, b, part);
+                        const int x = x0 + b;
+                        const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
+                        uint32_t nib = 0, nearb = 0;
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) acc[b][s] += part[s];
+                        for (int s = 0; s < 4; ++s) {
+                            const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
+                            const float e = MULT ? acc[b][s] : __builtin_amdgcn_exp2f(acc[b][s]);
+                            const float tt = fmaf(u, e, u - 1.0f);
+                            nib |= (uint32_t)(tt < 0.0f) << s;
+                            nearb |= (uint32_t)(fabsf(tt) <= dAv) << s;
+                        }
+                        if (nearb != 0 && active) {
+                            for (int s = 0; s < 4; ++s)
+                                if ((nearb >> s) & 1) {
+                                    const int pos = atomicAdd(&sh_qn, 1);
+                                    if (pos < QCAP) nearq[pos] = ((uint32_t)x << lgL) + (uint32_t)(y0 + s);
+                                }
+                        }
+                        store_nibble(vd, RS, L, x, m, nib, active);
                     }
-                    if (BH > 1) __builtin_amdgcn_sched_barrier(0);
                 }
-#pragma unroll
-                for (int b = 0; b < BH; ++b) {
-                    const int x = x0 + b;
-                    const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
-                    uint32_t nib = 0, nearb = 0;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const float u = fmaf((float)word_of(rn, s), 0x1p-32f, 0x1p-33f);
-                        const float tt = fmaf(u, __builtin_amdgcn_exp2f(acc[b][s]), u - 1.0f);
-                        nib |= (uint32_t)(tt < 0.0f) << s;
-                        nearb |= (uint32_t)(fabsf(tt) <= dAv) << s;
-                    }
-                    if (nearb != 0 && active) {
-                        for (int s = 0; s < 4; ++s)
-                            if ((nearb >> s) & 1) {
-                                const int pos = atomicAdd(&sh_qn, 1);
-                                if (pos < QCAP) nearq[pos] = ((uint32_t)x << lgL) + (uint32_t)(y0 + s);
-                            }
-                    }
-                    store_nibble(vd, RS, L, x, m, nib, active);
-                }
-            }
+            };
+            if (mult) visible_pass(flag_c<true>{});
+            else visible_pass(flag_c<false>{});
             __syncthreads();
             {
                 const int n = sh_qn;
@@ -552,51 +672,78 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         }
         // ---- F(x') with its error bound, E(x'), M(x')
         const uint32_t* vp = vpl + src * PL;
-        double Floc = 0.0;
-        for (int r = 0; r < nbrounds; ++r) {
-            const int Q = r * NT + tid;
-            const bool active = Q < nb;
-            const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
-            const int j0 = 4 * m;
-            uint32_t idx[BH + LW - 1][4];
+        // per-lane share of -sum softplus(a') over the lane's sites
+        auto fe_pass = [&](auto MT) -> double {
+            constexpr bool MULT = decltype(MT)::value;
+            double Floc = 0.0;
+            double D = 1.0;  // product mode: prod over sites of prod_k (1 + e^{a_k}), renormalised
+            int Dexp = 0;
+            for (int r = 0; r < nbrounds; ++r) {
+                const int Q = r * NT + tid;
+                const bool active = Q < nb;
+                const int i0 = active ? (Q >> lgq) * BH : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+                const int j0 = 4 * m;
+                uint32_t idx[BH + LW - 1][4];
 #pragma unroll
-            for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
-                const uint32_t w = window32(vp + ((i0 + r2) & Lm) * RS, j0);
+                for (int r2 = 0; r2 < BH + LW - 1; ++r2) {
+                    const uint32_t w = window32(vp + ((i0 + r2) & Lm) * RS, j0);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
-            }
-            // softplus(a) / ln 2 = max(z', 0) + log2(1 + 2^{-|z'|}) with z' = -z = a log2(e)
-            float msum[BH][4], prod[BH][4];
-#pragma unroll
-            for (int b = 0; b < BH; ++b)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    msum[b][s] = 0.f;
-                    prod[b][s] = 1.f;
+                    for (int s = 0; s < 4; ++s) idx[r2][s] = (w >> s) & (NP - 1);
                 }
-#pragma unroll KU
-            for (int k = 0; k < K; ++k) {
-#pragma unroll
-                for (int b = 0; b < BH; ++b) {
-                    float acc[4];
-                    table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], acc);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        msum[b][s] += fmaxf(-acc[s], 0.f);
-                        prod[b][s] = fmaf(prod[b][s], __builtin_amdgcn_exp2f(-fabsf(acc[s])), prod[b][s]);
-                    }
-                }
-                if (BH > 1) __builtin_amdgcn_sched_barrier(0);
-            }
-            if (active) {
-                float fs = 0.f;
+                // additive: softplus(a)/ln 2 = max(z', 0) + log2(1 + 2^{-|z'|}), z' = a log2(e)
+                float msum[BH][4], prod[BH][4];
 #pragma unroll
                 for (int b = 0; b < BH; ++b)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) fs += msum[b][s] + __builtin_amdgcn_logf(prod[b][s]);
-                Floc -= (double)fs * 0.693147180559945309;
+                    for (int s = 0; s < 4; ++s) {
+                        msum[b][s] = 0.f;
+                        prod[b][s] = 1.f;
+                    }
+#pragma unroll KUnroll<KT, BH>::value
+                for (int k = 0; k < K; ++k) {
+#pragma unroll
+                    for (int b = 0; b < BH; ++b) {
+                        if constexpr (MULT) {
+                            float e[4];
+                            table_prods_fwd<LW>(E1p + k * LW * NP, idx, b, ehbp[k], e);
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) prod[b][s] = fmaf(prod[b][s], e[s], prod[b][s]);
+                        } else {
+                            float acc[4];
+                            table_sums_fwd<LW>(T1 + k * LW * NP, idx, b, hbs[k], acc);
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                msum[b][s] += fmaxf(-acc[s], 0.f);
+                                prod[b][s] = fmaf(prod[b][s], __builtin_amdgcn_exp2f(-fabsf(acc[s])), prod[b][s]);
+                            }
+                        }
+                    }
+                    if (BH > 1) __builtin_amdgcn_sched_barrier(0);
+                }
+                if (active) {
+                    if constexpr (MULT) {
+#pragma unroll
+                        for (int b = 0; b < BH; ++b) {
+                            double q = (double)prod[b][0] * (double)prod[b][1];
+                            q *= (double)prod[b][2] * (double)prod[b][3];
+                            int ex;
+                            D = frexp(D * q, &ex);
+                            Dexp += ex;
+                        }
+                    } else {
+                        float fs = 0.f;
+#pragma unroll
+                        for (int b = 0; b < BH; ++b)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) fs += msum[b][s] + __builtin_amdgcn_logf(prod[b][s]);
+                        Floc -= (double)fs * 0.693147180559945309;
+                    }
+                }
             }
-        }
+            if constexpr (MULT) Floc = -(log(D) + (double)Dexp * 0.693147180559945309);
+            return Floc;
+        };
+        const double Floc = mult ? fe_pass(flag_c<true>{}) : fe_pass(flag_c<false>{});
         const double Fsp = block_sum(Floc, red);
         const double Bp = Bchain + 1e-13 * fabs(Fsp);
         long long Ep, Mp;
@@ -694,7 +841,7 @@ int ising_fast_threads(int L)
 size_t ising_fast_lds_bytes(int K, int LW, int L)
 {
     const size_t tsz = (size_t)K * LW * ((size_t)1 << LW);
-    size_t o = ((2 * tsz + 4 * (size_t)K) * 4 + 15) & ~(size_t)15;
+    size_t o = ((3 * tsz + 6 * (size_t)K) * 4 + 15) & ~(size_t)15;
     o += 64 * 8;
     const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
     o += (3 + (size_t)K) * (size_t)L * RS * 4;

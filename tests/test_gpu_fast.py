@@ -122,6 +122,41 @@ def test_resume_is_bitwise(api):
         assert np.array_equal(sa[name], sc[name])
 
 
+def _filter_sums(f):
+    """S_k = |h_b| + sum |W_k| per channel and S_v = |b| + sum |W| (C = 1)."""
+    Sk = np.abs(f.hbias.astype(np.float64)) + np.abs(f.W.astype(np.float64)).reshape(f.W.shape[0], -1).sum(1)
+    Sv = abs(float(f.vbias[0])) + float(np.abs(f.W.astype(np.float64)).sum())
+    return Sk, Sv
+
+
+@pytest.mark.parametrize("case", ["product_near_limit", "additive_large_filters", "additive_one_channel"])
+def test_table_modes(orc, api, case):
+    # The kernel evaluates e^{-a} as products of tabulated exponentials while every
+    # partial product stays inside float32 range (S_k, S_v < 80, sum_k S_k + K < 80),
+    # and as exp2 of tabulated sums otherwise; both must reproduce the oracle.
+    rng = np.random.default_rng(11)
+    if case == "product_near_limit":
+        K, Lw = 2, 5
+        W = (rng.choice([-1.0, 1.0], (K, 1, Lw, Lw)) * 1.42).astype(np.float32)
+        f = WL.Filters(W, np.array([0.3, -0.2], np.float32), np.array([0.1], np.float32))
+        Sk, Sv = _filter_sums(f)
+        assert Sk.max() < 80 and Sv < 80 and Sk.sum() + K < 80 and Sv > 70
+    elif case == "additive_large_filters":
+        K, Lw = 8, 5
+        f = WL.random_filters_with_bias(K, 1, Lw, 1.0, 0.5, seed=5)
+        Sk, Sv = _filter_sums(f)
+        assert Sk.sum() + K > 80
+    else:
+        K, Lw = 1, 3
+        W = (rng.choice([-1.0, 1.0], (K, 1, Lw, Lw)) * 9.5).astype(np.float32)
+        f = WL.Filters(W, np.array([0.4], np.float32), np.array([-0.3], np.float32))
+        Sk, Sv = _filter_sums(f)
+        assert Sk.max() > 80
+    T = np.linspace(1.2, 4.0, 8)
+    job, ch = run_pair(orc, api, f, 32, T, seed=21, sweeps=12, burnin=2, blocks=[5, 7])
+    check_chains(orc, job, ch, 1e-9)
+
+
 @pytest.mark.parametrize("L", [32, 64])
 def test_tile_shapes_give_identical_chains(orc, api, L):
     # every (rows, threads) tile choice yields the same chains (doubles as a race check)
