@@ -36,6 +36,18 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return {c0, c1, c2, c3};
 }
 
+// The same generator for a key that is uniform across the wave: the key is kept
+// in two scalar registers and advanced per round at every call, instead of a
+// twenty-register schedule that the compiler would hold across the caller's loops.
+__device__ __forceinline__ u32x4 philox10_uk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1)
+{
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return philox10(c0, c1, c2, c3, k0, k1);
+}
+
 enum : uint32_t { STREAM_INIT = 0, STREAM_HID = 1, STREAM_VIS = 2, STREAM_MH = 3 };
 
 __device__ __forceinline__ uint32_t word_of(const u32x4& r, int w)
@@ -99,25 +111,53 @@ __host__ __device__ inline float gamma_f32(int n)
 // ---------------------------------------------------------------------------
 // Reductions (wave64)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
+// Butterfly over each 32-lane half with ds_swizzle (xor mode: and-mask 31,
+// xor-mask X), which takes its lane pattern as an immediate, then the two
+// half sums via readlane.  Needs the whole wave active; the result is
+// wave-uniform and identical in every lane.
+template <int X>
+__device__ __forceinline__ int swz_xor(int v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
 }
 
-__device__ __forceinline__ long long wave_sum(long long v)
+template <int X>
+__device__ __forceinline__ long long swz_xor(long long v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const int lo = swz_xor<X>((int)(uint32_t)v);
+    const int hi = swz_xor<X>((int)(v >> 32));
+    return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__device__ __forceinline__ int wave_sum(int v)
+template <int X>
+__device__ __forceinline__ double swz_xor(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return __longlong_as_double(swz_xor<X>(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ int readlane_t(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ long long readlane_t(long long v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_t(double v, int l)
+{
+    return __longlong_as_double(readlane_t(__double_as_longlong(v), l));
+}
+
+template <typename Tv>
+__device__ __forceinline__ Tv wave_sum(Tv v)
+{
+    v += swz_xor<16>(v);
+    v += swz_xor<8>(v);
+    v += swz_xor<4>(v);
+    v += swz_xor<2>(v);
+    v += swz_xor<1>(v);
+    return readlane_t(v, 0) + readlane_t(v, 32);
 }
 
 // Workgroup sum; `red` is LDS scratch of >= nwaves entries.  Every thread

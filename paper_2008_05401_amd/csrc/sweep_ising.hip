@@ -132,6 +132,83 @@ __device__ void ising_em_bits(const uint32_t* pl, int L, int RS, long long* red,
     M = 2LL * so - (long long)L * L;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 exp and log for the exact paths inside the sweep loop, with every
+// constant read from a small LDS table: nothing of them is then held in
+// registers across the hot passes.  exp: Cody-Waite reduction x = k ln2 + r
+// (ln2 split as in fdlibm so that k ln2_hi is exact), Taylor series of e^r to
+// r^13 (|r| <= ln2/2, truncation < 1e-17).  log: x = 2^e m, m in [sqrt(1/2),
+// sqrt(2)), log m = 2 atanh(s) with s = (m-1)/(m+1), series to s^23.
+// ---------------------------------------------------------------------------
+constexpr int NDC = 27;
+enum { DC_LN2HI = 0, DC_LN2LO = 1, DC_INVLN2 = 2, DC_FACT = 3, DC_ODD = 15, DC_SQRTH = 26 };
+
+__device__ inline void fill_dconst(double* c)
+{
+    c[DC_LN2HI] = 6.93147180369123816490e-01;
+    c[DC_LN2LO] = 1.90821492927058770002e-10;
+    c[DC_INVLN2] = 1.44269504088896338700e+00;
+    double f = 1.0;
+    for (int n = 2; n <= 13; ++n) {
+        f *= (double)n;
+        c[DC_FACT + n - 2] = 1.0 / f;  // 1/n!
+    }
+    for (int n = 1; n <= 11; ++n) c[DC_ODD + n - 1] = 1.0 / (double)(2 * n + 1);
+    c[DC_SQRTH] = 0.70710678118654752440;
+}
+
+__device__ __forceinline__ double exp_c(double x, const double* c)
+{
+    const double kd = rint(x * c[DC_INVLN2]);
+    double r = fma(-kd, c[DC_LN2HI], x);
+    r = fma(-kd, c[DC_LN2LO], r);
+    double p = c[DC_FACT + 11];
+#pragma unroll
+    for (int n = 12; n >= 2; --n) p = fma(p, r, c[DC_FACT + n - 2]);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)kd);
+}
+
+// x > 0, finite
+__device__ __forceinline__ double log_c(double x, const double* c)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < c[DC_SQRTH]) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double q = c[DC_ODD + 10];
+#pragma unroll
+    for (int n = 10; n >= 1; --n) q = fma(q, z, c[DC_ODD + n - 1]);
+    const double lm = fma(2.0 * s, z * q, 2.0 * s);
+    return fma((double)e, c[DC_LN2HI], fma((double)e, c[DC_LN2LO], lm));
+}
+
+// log(1 + y), y >= 0
+__device__ __forceinline__ double log1p_c(double y, const double* c)
+{
+    const double u = 1.0 + y;
+    if (u == 1.0) return y;
+    return log_c(u, c) * (y / (u - 1.0));
+}
+
+__device__ __forceinline__ double softplus_c(double x, const double* c)
+{
+    return (x > 0.0 ? x : 0.0) + log1p_c(exp_c(-fabs(x), c), c);
+}
+
+// h = [u < sigmoid(a)], u = (x + 0.5) 2^-32, in FP64
+__device__ __forceinline__ bool bernoulli_exact_c(double a, uint32_t x, const double* c)
+{
+    const double u = ((double)x + 0.5) * 0x1p-32;
+    return u < 1.0 / (1.0 + exp_c(-a, c));
+}
+
 template <int LW>
 __device__ __forceinline__ double preact_h_exact(const float* __restrict__ W, float hb, const uint32_t* pl, int RS,
                                                  int L, int k, int i, int j)
@@ -177,13 +254,13 @@ __device__ __forceinline__ double preact_v_exact(const float* __restrict__ W, fl
 // FP64 free energy of a bit plane, over the workgroup
 template <int LW>
 __device__ double free_energy_exact(const float* __restrict__ W, const float* hbs, float vb, const uint32_t* pl,
-                                    int RS, int L, int K, double* red)
+                                    int RS, int L, int K, double* red, const double* dc)
 {
     const int LL = L * L;
     double f = 0.0;
     for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        f -= softplus_d(preact_h_exact<LW>(W, hbs[k], pl, RS, L, k, i, j));
+        f -= softplus_c(preact_h_exact<LW>(W, hbs[k], pl, RS, L, k, i, j), dc);
     }
     for (int q = threadIdx.x; q < LL; q += blockDim.x) {
         const int i = q / L, j = q - i * L;
@@ -362,6 +439,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     __shared__ int sh_qn;
     __shared__ ChainRec R;
     __shared__ double sh_Bcur;
+    constexpr int LU_CHUNK = 64;
+    __shared__ double sh_lu[LU_CHUNK];
+    __shared__ double sh_dc[NDC];
+    __shared__ long long sh_Mcur;
+    __shared__ int sh_cur;
+    __shared__ double sh_Bchain;
 
     const float* __restrict__ W = J.W;
     constexpr float NLOG2E = -1.44269504088896341f;
@@ -383,6 +466,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         sh_evbm = (float)exp(-(double)vb);
         sh_Sv = s;
     }
+    if (tid == NT - 1) fill_dconst(sh_dc);
     __syncthreads();
     // Product mode when every partial product stays well inside the float32
     // normal range: |log| of a hidden factor chain <= S_k, of a visible chain
@@ -459,11 +543,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         sh_Bcur = R.reserved[0];
     }
     __syncthreads();
-    long long Ecur_d, Mcur;
-    ising_em_bits(vpl, L, RS, (long long*)red, Ecur_d, Mcur);
-    const double beta = 1.0 / J.T[g];
-    const uint32_t t0 = (uint32_t)sh_t0;
-    const float vb = sh_vb, dAv = sh_dAv, vb_raw = sh_vb_raw, evbm = sh_evbm;
+    {
+        long long Ecur_d, Mcur;
+        ising_em_bits(vpl, L, RS, (long long*)red, Ecur_d, Mcur);
+        if (tid == 0) {
+            sh_Mcur = Mcur;
+            sh_cur = 0;
+        }
+    }
+    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_t0);
     // rigorous bound of the float32 free energy per site
     //   product mode: K factors (1 + e^{a_k}) with e^{a_k} from 2 LW + 1 roundings,
     //   one rounding per product step; the FP64 log of the product is exact enough;
@@ -473,12 +561,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     const double Bsite = mult ? (double)K * ((double)gamma_f32(2 * LW + 1) + 0x1p-24) * 1.02
                               : (double)dAsum + (double)(K + 2) * 0x1p-20 +
                                     (double)(K + 2) * 0x1p-24 * 1.5 * (double)Ssum;
-    const double Bchain = Bsite * (double)L * (double)L;
+    // product mode adds, per lane, the float log2 of a number in [0.5, 1]: its
+    // rounding to float and the log2 instruction stay below 2^-21 (natural log units)
+    if (tid == 0) sh_Bchain = Bsite * (double)L * (double)L + (mult ? (double)NT * 0x1p-21 : 0.0);
+    __syncthreads();
 
-    int cur = 0;
-    int nre = 0, nre_mh = 0;
+    // State that lives across the passes (current plane, M of the current state,
+    // chain bound) stays in LDS: the passes use every vector register.
     for (int it = 0; it < P.n_sweeps; ++it) {
+        const int cur = __builtin_amdgcn_readfirstlane(sh_cur);
         const uint32_t t = t0 + (uint32_t)it;
+        // log of the MH uniforms of the next LU_CHUNK sweeps, one per lane
+        if ((it & (LU_CHUNK - 1)) == 0) {
+            if (tid < LU_CHUNK && it + tid < P.n_sweeps) sh_lu[tid] = log_c(mh_uniform(J.seed, t + (uint32_t)tid, gid), sh_dc);
+            __syncthreads();
+        }
         int src = cur;
         for (int sub = 0; sub < J.gibbs_k; ++sub) {
             int dst = src == 2 ? 0 : src + 1;
@@ -521,7 +618,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                                 for (int s = 0; s < 4; ++s) e[s] = __builtin_amdgcn_exp2f(z[s]);
                             }
                             const u32x4 rn =
-                                philox10((uint32_t)((((k << lgL) + i) << lgL) + j0) >> 2, t, gid, tagh, k0, k1);
+                                philox10_uk((uint32_t)((((k << lgL) + i) << lgL) + j0) >> 2, t, gid, tagh, k0, k1);
                             uint32_t nib = 0, nearb = 0;
 #pragma unroll
                             for (int s = 0; s < 4; ++s) {
@@ -550,27 +647,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             __syncthreads();
             {
                 // FP64 decisions of the queued hidden units (exact-mode rescan on overflow)
-                const int n = sh_qn;
+                const int n = __builtin_amdgcn_readfirstlane(sh_qn);
                 if (n > 0) {
                     if (n <= QCAP) {
                         for (int e = tid; e < n; e += NT) {
                             const uint32_t q = nearq[e];
                             const int k = (int)(q >> (2 * lgL)), i = (int)(q >> lgL) & Lm, j = (int)q & Lm;
-                            const u32x4 rn = philox10(q >> 2, t, gid, tagh, k0, k1);
+                            const u32x4 rn = philox10_uk(q >> 2, t, gid, tagh, k0, k1);
                             const bool on =
-                                bernoulli_exact(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3));
+                                bernoulli_exact_c(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
                             put_bit(hpl + k * PL, RS, L, i, j, on);
                         }
                     } else {
                         for (int q = tid; q < (K << (2 * lgL)); q += NT) {
                             const int k = q >> (2 * lgL), i = (q >> lgL) & Lm, j = q & Lm;
-                            const u32x4 rn = philox10((uint32_t)q >> 2, t, gid, tagh, k0, k1);
+                            const u32x4 rn = philox10_uk((uint32_t)q >> 2, t, gid, tagh, k0, k1);
                             const bool on =
-                                bernoulli_exact(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3));
+                                bernoulli_exact_c(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
                             put_bit(hpl + k * PL, RS, L, i, j, on);
                         }
                     }
-                    nre += tid == 0 ? n : 0;
+                    if (tid == 0) R.n_recheck += n;
                     __syncthreads();
                     if (tid == 0) sh_qn = 0;
                     __syncthreads();
@@ -579,6 +676,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             // ---- visible pass: v' ~ P(v | h)
             auto visible_pass = [&](auto MT) {
                 constexpr bool MULT = decltype(MT)::value;
+                const float vb = sh_vb, evbm = sh_evbm, dAv = sh_dAv;
                 for (int r = 0; r < nbrounds; ++r) {
                     const int Q = r * NT + tid;
                     const bool active = Q < nb;
@@ -619,7 +717,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
 #pragma unroll
                     for (int b = 0; b < BH; ++b) {
                         const int x = x0 + b;
-                        const u32x4 rn = philox10((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
+                        const u32x4 rn = philox10_uk((uint32_t)((x << lgL) + y0) >> 2, t, gid, tagv, k0, k1);
                         uint32_t nib = 0, nearb = 0;
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
@@ -644,27 +742,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             else visible_pass(flag_c<false>{});
             __syncthreads();
             {
-                const int n = sh_qn;
+                const int n = __builtin_amdgcn_readfirstlane(sh_qn);
                 if (n > 0) {
                     if (n <= QCAP) {
                         for (int e = tid; e < n; e += NT) {
                             const uint32_t q = nearq[e];
                             const int x = (int)(q >> lgL), y = (int)q & Lm;
-                            const u32x4 rn = philox10(q >> 2, t, gid, tagv, k0, k1);
+                            const u32x4 rn = philox10_uk(q >> 2, t, gid, tagv, k0, k1);
                             const bool on =
-                                bernoulli_exact(preact_v_exact<LW>(W, vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3));
+                                bernoulli_exact_c(preact_v_exact<LW>(W, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
                             put_bit(vd, RS, L, x, y, on);
                         }
                     } else {
                         for (int q = tid; q < (1 << (2 * lgL)); q += NT) {
                             const int x = q >> lgL, y = q & Lm;
-                            const u32x4 rn = philox10((uint32_t)q >> 2, t, gid, tagv, k0, k1);
+                            const u32x4 rn = philox10_uk((uint32_t)q >> 2, t, gid, tagv, k0, k1);
                             const bool on =
-                                bernoulli_exact(preact_v_exact<LW>(W, vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3));
+                                bernoulli_exact_c(preact_v_exact<LW>(W, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
                             put_bit(vd, RS, L, x, y, on);
                         }
                     }
-                    nre += tid == 0 ? n : 0;
+                    if (tid == 0) R.n_recheck += n;
                     __syncthreads();
                 }
             }
@@ -740,40 +838,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                     }
                 }
             }
-            if constexpr (MULT) Floc = -(log(D) + (double)Dexp * 0.693147180559945309);
+            // D in [0.5, 1]: float log2 of it, error counted in the chain bound
+            if constexpr (MULT)
+                Floc = -((double)__builtin_amdgcn_logf((float)D) + (double)Dexp) * 0.693147180559945309;
             return Floc;
         };
         const double Floc = mult ? fe_pass(flag_c<true>{}) : fe_pass(flag_c<false>{});
         const double Fsp = block_sum(Floc, red);
-        const double Bp = Bchain + 1e-13 * fabs(Fsp);
+        const double Bp = sh_Bchain + 1e-13 * fabs(Fsp);
         long long Ep, Mp;
         ising_em_bits(vp, L, RS, (long long*)red, Ep, Mp);
         const long long ones = (Mp + (long long)L * L) / 2;
-        const double Fp = Fsp - (double)vb_raw * (double)ones;
+        const double Fp = Fsp - (double)sh_vb_raw * (double)ones;
         double lu = 0.0;
         if (tid == 0) {
-            const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
-            lu = log(mh_uniform(J.seed, t, gid));
+            const double logr = -(1.0 / J.T[g]) * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
+            lu = sh_lu[it & (LU_CHUNK - 1)];
             const double band = Bp + sh_Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
             sh_flag = J.target == 2 ? 1 : ((fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2);
         }
         __syncthreads();
-        int flag = sh_flag;
+        int flag = __builtin_amdgcn_readfirstlane(sh_flag);
         double Fnew = Fp, Bnew = Bp, Fold = 0.0;
         if (flag == 2) {
             // inside the float32 band: decide with FP64 free energies of both states
-            Fnew = free_energy_exact<LW>(W, J.hb, vb_raw, vp, RS, L, K, red);
-            Fold = free_energy_exact<LW>(W, J.hb, vb_raw, vpl + cur * PL, RS, L, K, red);
+            Fnew = free_energy_exact<LW>(W, J.hb, sh_vb_raw, vp, RS, L, K, red, sh_dc);
+            Fold = free_energy_exact<LW>(W, J.hb, sh_vb_raw, vpl + cur * PL, RS, L, K, red, sh_dc);
             Bnew = 0.0;
             if (tid == 0) {
-                const double logr = -beta * J.J0 * (double)(Ep - R.E) + (Fnew - Fold);
+                const double logr = -(1.0 / J.T[g]) * J.J0 * (double)(Ep - R.E) + (Fnew - Fold);
                 sh_flag = lu < logr ? 1 : 0;
                 R.F = Fold;
                 sh_Bcur = 0.0;
-                ++nre_mh;
+                R.n_recheck += 1;
             }
             __syncthreads();
-            flag = sh_flag;
+            flag = __builtin_amdgcn_readfirstlane(sh_flag);
         }
         if (tid == 0) {
             if (flag) {
@@ -784,7 +884,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             }
             R.sweeps += 1;
             if ((long long)t >= (long long)J.burnin) {
-                const long long mm = flag ? Mp : Mcur;
+                const long long mm = flag ? Mp : sh_Mcur;
                 R.n_meas += 1;
                 R.sumE += R.E;
                 R.sumE2 += R.E * R.E;
@@ -793,12 +893,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                 R.sumM2 += mm * mm;
             }
         }
-        if (flag) {
-            cur = src;
-            Mcur = Mp;
+        if (flag && tid == 0) {
+            sh_cur = src;
+            sh_Mcur = Mp;
         }
         __syncthreads();
     }
+    const int cur = __builtin_amdgcn_readfirstlane(sh_cur);
     // store the state
     for (int r = 0; r < nrounds; ++r) {
         const int Q = r * NT + tid;
@@ -810,9 +911,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             *(uint32_t*)(state + (i << lgL) + 4 * m) = up | (dn * 0xFFu);
         }
     }
-    const int tot = block_sum(nre, (int*)red);
     if (tid == 0) {
-        R.n_recheck += tot + nre_mh;
         R.reserved[0] = sh_Bcur;
         *rec = R;
     }
