@@ -30,6 +30,37 @@ import numpy as np  # noqa: E402
 # MI355X published peaks used for the roofline
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
+
+# HBM bytes of one sweep-kernel launch of this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# counter reads for a plain 256 MiB device-to-device copy (x2.0 and x1.0).  The
+# figure holds only for the kernel sources it was taken with (their SHA-256);
+# after any change to them `traffic` is reported as null until re-measured.
+KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
+                  "paper_2008_05401_amd/csrc/sweep_common.h")
+MEASURED_TRAFFIC = {"sources_sha256": "32845f392c8fefd08dc36ea1917497c485e4f8cb85796b6b26be899ee8f27f56",
+                    "chains": 4096, "L": 64, "sweeps_per_launch": 100,
+                    "fetch_kib": 9343.2, "fetch_scale": 2.0, "write_kib": 21156.3, "write_scale": 1.0}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes(chains, L, sweeps_per_launch):
+    m = MEASURED_TRAFFIC
+    if (chains, L, sweeps_per_launch) != (m["chains"], m["L"], m["sweeps_per_launch"]):
+        return None
+    if kernel_sources_sha256() != m["sources_sha256"]:
+        return None
+    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
 def conv_flops_per_site_sweep(K, C, Lw, gibbs_k=1):
@@ -37,6 +68,13 @@ def conv_flops_per_site_sweep(K, C, Lw, gibbs_k=1):
     v->h and h->v' (gibbs_k times) and v'->a' for F(x'), K*C*Lw^2
     multiply-adds each, 2 flops per multiply-add."""
     return 2.0 * K * C * Lw * Lw * (2 * gibbs_k + 1)
+
+
+def lds_table_bytes_per_site_sweep(K, C, Lw, gibbs_k=1):
+    """LDS bytes of the subset-sum/product table reads of one sweep per site:
+    one float per (channel, filter row) in each of the hidden, visible and
+    free-energy passes."""
+    return 4.0 * K * C * Lw * (2 * gibbs_k + 1)
 
 
 def cpu_baseline(f, T, L, seed, seconds=15.0):
@@ -247,6 +285,8 @@ def main():
     sweeps_per_launch = full[0][0]
     flops_per_launch = conv_flops_per_site_sweep(K, C, Lw) * n * L * L * sweeps_per_launch
     achieved_tflops = flops_per_launch / avg_launch_s / 1e12
+    # state read and written once (int8 per site) plus the per-chain records read and written
+    algo_bytes = 2.0 * n * L * L + 2.0 * n * 160
 
     site_sweeps = n * L * L * args.steps
     value = site_sweeps / wall
@@ -276,13 +316,18 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic_bytes(n, L, sweeps_per_launch),
+            "traffic_unit": "HBM bytes per launch",
+            "algorithmic_bytes_per_launch": algo_bytes,
             "kernel_avg_ms": avg_launch_s * 1e3,
             "algorithmic_flops_per_site_sweep": conv_flops_per_site_sweep(K, C, Lw),
-            "hbm_algorithmic_GBps": 2.0 * n * L * L / avg_launch_s / 1e9,
-            "hbm_frac": 2.0 * n * L * L / avg_launch_s / 1e9 / PEAK_HBM_GBS,
+            "hbm_algorithmic_GBps": algo_bytes / avg_launch_s / 1e9,
+            "hbm_frac": algo_bytes / avg_launch_s / 1e9 / PEAK_HBM_GBS,
         },
     }
+    lds_tbs = lds_table_bytes_per_site_sweep(K, C, Lw) * n * L * L * sweeps_per_launch / avg_launch_s / 1e12
+    out["lds"] = {"table_bytes_per_site_sweep": lds_table_bytes_per_site_sweep(K, C, Lw), "achieved": lds_tbs,
+                  "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds_tbs / PEAK_LDS_TBS}
     if not args.no_extra:
         out["kitaev"] = kitaev()
         out["training"] = training_and_transfer()
