@@ -21,12 +21,12 @@ _SRC = os.path.join(_HERE, "crbm_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 ISING, KITAEV, GIBBS = 0, 1, 2
-ST_INIT, ST_HID, ST_VIS, ST_MH = 0, 1, 2, 3
+ST_INIT, ST_HID, ST_VIS, ST_MH, ST_PT = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle library in-tree with gcc."""
-    if force or not os.path.exists(_LIB):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                "-shared", "-std=c11", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
@@ -49,7 +49,7 @@ CHAIN_DTYPE = np.dtype([
     ("sweeps", "<i8"), ("n_acc", "<i8"), ("n_meas", "<i8"), ("pad0", "<i8"),
     ("sumE", "<i8"), ("sumE2", "<i8"), ("sumM", "<i8"), ("sumAbsM", "<i8"), ("sumM2", "<i8"),
     ("E", "<i8"), ("F", "<f8"), ("S", "<f8"), ("Ef", "<f8"), ("Cf", "<f8"),
-    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"),
+    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"), ("n_swap", "<i8"),
 ])
 
 _lib = None
@@ -85,8 +85,11 @@ def lib():
         L.orc_gibbs_step.argtypes = [P(_Params), ct.c_int, vp, vp, vp, ct.c_uint64, ct.c_uint32,
                                      ct.c_uint32, ct.c_uint32, vp]
         L.orc_gibbs_step.restype = ct.c_int64
-        L.orc_chain_init.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp]
-        L.orc_run.argtypes = [P(_Params), P(_RunDesc), vp, vp, ct.c_uint32, ct.c_int, vp, vp, vp]
+        L.orc_chain_init.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp, vp]
+        L.orc_run.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp, vp, ct.c_uint32, ct.c_int, vp, vp, vp]
+        L.orc_tempering_swap.argtypes = [P(_RunDesc), ct.c_int, vp, vp, vp, vp, ct.c_int, ct.c_uint32, vp]
+        L.orc_pt_uniform.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_uint32]
+        L.orc_pt_uniform.restype = ct.c_double
         L.orc_grad.argtypes = [P(_Params), vp, ct.c_int, ct.c_int, vp, vp, vp, vp]
         L.orc_num_threads.restype = ct.c_int
         _lib = L
@@ -239,30 +242,59 @@ def init_state(seed: int, n: int, C: int, L: int, g0: int = 0) -> np.ndarray:
     return s
 
 
+def pt_uniform(seed: int, r: int, g: int) -> float:
+    return float(lib().orc_pt_uniform(seed, r, g))
+
+
 class Chains:
-    """n independent chains of the CRBM-proposal + MH sampler (FP64)."""
+    """n independent chains of the CRBM-proposal + MH sampler (FP64).
+
+    replica=True gives every chain a persistent CRBM replica (exchange
+    correction); its initial state is a copy of the chain's (or `rbm_state`).
+    tempering_swap() does one round of temperature swaps on the ladder grid
+    chain = rung * n_ladders + ladder.  ties[0]: Gibbs near-ties, ties[1]: MH
+    near-ties, ties[2]: swap near-ties."""
 
     def __init__(self, m: CRBM, target_kind: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
-                 burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, g0: int = 0):
+                 burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, g0: int = 0, replica: bool = False,
+                 rbm_state=None):
         self.m = m
+        self.L = L
         self.T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
         n = self.T.shape[0]
         self.state = (init_state(seed, n, m.C, L, g0) if state is None
                       else np.array(state, dtype=np.int8, order="C", copy=True))
         assert self.state.shape == (n, m.C, L, L)
+        self.rbm = None
+        if replica or rbm_state is not None:
+            self.rbm = (self.state.copy() if rbm_state is None
+                        else np.array(rbm_state, dtype=np.int8, order="C", copy=True))
+            assert self.rbm.shape == self.state.shape
         self.desc = _RunDesc(target_kind, L, n, gibbs_k, burnin, g0, seed, (ct.c_double * 3)(*J))
         self.rec = np.zeros(n, CHAIN_DTYPE)
+        self.eps = np.zeros((n, L * L), np.float64) if target_kind == 1 else None
         self.t = 0
-        self.ties = np.zeros(2, np.int64)
-        lib().orc_chain_init(m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state), _ptr(self.rec))
+        self.ties = np.zeros(3, np.int64)
+        lib().orc_chain_init(m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state), _ptr(self.rec),
+                             _ptr(self.eps) if self.eps is not None else None)
 
     def run(self, n_sweeps: int, log_accepts: bool = False):
         n = self.T.shape[0]
         acc = np.zeros((n, n_sweeps), np.uint8) if log_accepts else None
-        lib().orc_run(self.m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state), self.t, n_sweeps,
+        lib().orc_run(self.m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state),
+                      _ptr(self.rbm) if self.rbm is not None else None,
+                      _ptr(self.eps) if self.eps is not None else None, self.t, n_sweeps,
                       _ptr(self.rec), _ptr(self.ties), _ptr(acc) if acc is not None else None)
         self.t += n_sweeps
         return acc
+
+    def tempering_swap(self, n_ladders: int, round_: int):
+        n = self.T.shape[0]
+        assert n % n_ladders == 0
+        tie = np.zeros(1, np.int64)
+        lib().orc_tempering_swap(ct.byref(self.desc), self.m.C, _ptr(self.T), _ptr(self.state), _ptr(self.rec),
+                                 _ptr(self.eps) if self.eps is not None else None, n_ladders, round_, _ptr(tie))
+        self.ties[2] += tie[0]
 
 
 def num_threads() -> int:

@@ -31,6 +31,15 @@
  *     is reversible with respect to exp(-F) (App. B, Gibbs sampling), the
  *     acceptance ratio of Eq. (acceptance) with one replica being the CRBM
  *     reduces to  log r = log P(x') - log P(x) + F(x') - F(x).
+ *     Two forms: the CRBM replica refreshed from the physical state before
+ *     every sweep, or a persistent CRBM replica y that the Gibbs steps advance
+ *     and that is exchanged with the physical state x (App. B, parallel
+ *     tempering with an exchange correction): accepted -> x <- y', y <- x.
+ *   - temperature swaps of parallel tempering (Eq. (acceptance) between two
+ *     physical temperatures), stream PT=4: chains sit on a ladder grid,
+ *     chain g = rung * n_ladders + ladder; round r pairs rungs (q, q+1) for
+ *     q = r%2, r%2+2, ...; the uniform of a pair is the 53-bit MH-form
+ *     uniform of counter (0, r, chain index of the lower rung, PT).
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,7 +84,7 @@ ORC_API void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uin
     memcpy(out, c, sizeof c);
 }
 
-enum { ST_INIT = 0, ST_HID = 1, ST_VIS = 2, ST_MH = 3 };
+enum { ST_INIT = 0, ST_HID = 1, ST_VIS = 2, ST_MH = 3, ST_PT = 4 };
 
 /* the 32-bit word that belongs to unit q of a stream */
 static uint32_t unit_word(uint64_t seed, uint32_t q, uint32_t t, uint32_t g, uint32_t tag)
@@ -89,16 +98,22 @@ static uint32_t unit_word(uint64_t seed, uint32_t q, uint32_t t, uint32_t g, uin
 
 static double word_to_unit_interval(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
 
-/* 53-bit MH uniform of chain g at sweep t, in (0,1) */
-ORC_API double orc_mh_uniform(uint64_t seed, uint32_t t, uint32_t g)
+/* 53-bit uniform in (0,1) from words 0,1 of unit group 0 of a stream */
+static double uniform53(uint64_t seed, uint32_t t, uint32_t g, uint32_t tag)
 {
-    const uint32_t ctr[4] = {0u, t, g, (uint32_t)ST_MH};
+    const uint32_t ctr[4] = {0u, t, g, tag};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
     const uint64_t x = ((uint64_t)out[0] << 32) | (uint64_t)out[1];
     return ((double)(x >> 11) + 0.5) * 0x1p-53;
 }
+
+/* 53-bit MH uniform of chain g at sweep t, in (0,1) */
+ORC_API double orc_mh_uniform(uint64_t seed, uint32_t t, uint32_t g) { return uniform53(seed, t, g, ST_MH); }
+
+/* 53-bit uniform of a temperature swap: round r, chain index g of the lower rung */
+ORC_API double orc_pt_uniform(uint64_t seed, uint32_t r, uint32_t g) { return uniform53(seed, r, g, ST_PT); }
 
 /* Bernoulli uniform of unit q in stream `tag` */
 ORC_API double orc_unit_uniform(uint64_t seed, uint32_t q, uint32_t t, uint32_t g, uint32_t tag)
@@ -371,6 +386,7 @@ typedef struct {
     double F;                                   /* CRBM free energy of current state */
     double S, Ef, Cf;                           /* Kitaev -beta F, fermion energy, fluctuation */
     double kE, kE2, kCf;                        /* Kitaev sums */
+    int64_t n_swap;                             /* accepted temperature swaps */
 } orc_chain;
 
 typedef struct {
@@ -383,7 +399,7 @@ typedef struct {
 
 /* record of the current state: cached F and target, zeroed sums */
 ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const double* T,
-                            const int8_t* state, orc_chain* rec)
+                            const int8_t* state, orc_chain* rec, double* eps)
 {
     const int C = P->C, L = D->L, nv = C * L * L;
 #pragma omp parallel
@@ -400,7 +416,8 @@ ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const do
             if (D->target != 1) {
                 R->E = orc_ising_energy(s, L);
             } else {
-                R->S = orc_kitaev_S(s, C, L, D->J, 1.0 / T[g], NULL, &R->Ef, &R->Cf);
+                R->S = orc_kitaev_S(s, C, L, D->J, 1.0 / T[g], eps ? eps + (size_t)g * L * L : NULL, &R->Ef,
+                                    &R->Cf);
             }
         }
         free(v);
@@ -409,14 +426,18 @@ ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const do
 }
 
 /* n_sweeps propose+accept sweeps of every chain, starting at sweep index t0.
- * One sweep: gibbs_k Gibbs steps from the current state give x'; then
+ * One sweep: gibbs_k Gibbs steps from the current state (or, with `rbm` not
+ * NULL, from the chain's persistent CRBM replica) give x'; then
  * Ising:  log r = -beta J (E(x') - E(x)) + F(x') - F(x)
  * Kitaev: log r =  S(x') - S(x)          + F(x') - F(x)
  * accept iff log u < log r.  After burn-in (sweep index >= burnin) the
  * observables of the state after the sweep are accumulated.
+ * With a replica: accepted -> state <- x', replica <- old state; rejected ->
+ * replica <- x'.  For Kitaev, `eps` (if not NULL) keeps the singular values
+ * of every chain's current state, [n_chains][L*L].
  * ties[0] counts Gibbs near-ties, ties[1] counts |log r - log u| < 1e-6.  */
-ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T, int8_t* state,
-                     uint32_t t0, int n_sweeps, orc_chain* rec, int64_t* ties, uint8_t* accept_log)
+ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T, int8_t* state, int8_t* rbm,
+                     double* eps, uint32_t t0, int n_sweeps, orc_chain* rec, int64_t* ties, uint8_t* accept_log)
 {
     const int C = P->C, L = D->L, n = L * L, nv = C * n;
     int64_t gt = 0, mt = 0;
@@ -427,15 +448,17 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
         uint8_t* h = (uint8_t*)malloc((size_t)P->K * n);
         double* a = (double*)malloc(sizeof(double) * (size_t)(P->K > C ? P->K : C) * n);
         int8_t* sp = (int8_t*)malloc((size_t)nv);
+        double* epsp = (double*)malloc(sizeof(double) * (size_t)n);
 #pragma omp for schedule(dynamic)
         for (int g = 0; g < D->n_chains; ++g) {
             int8_t* s = state + (size_t)g * nv;
+            int8_t* y = rbm ? rbm + (size_t)g * nv : NULL;
             orc_chain* R = rec + g;
             const double beta = 1.0 / T[g];
             const uint32_t gid = D->g0 + (uint32_t)g;
             for (int it = 0; it < n_sweeps; ++it) {
                 const uint32_t t = t0 + (uint32_t)it;
-                spins_to_visible(s, C, L, v);
+                spins_to_visible(y ? y : s, C, L, v);
                 for (int k = 0; k < D->gibbs_k; ++k) {
                     gt += orc_gibbs_step(P, L, v, h, v2, D->seed, t, gid, (uint32_t)k, a);
                     memcpy(v, v2, (size_t)nv);
@@ -449,7 +472,7 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                     Ep = orc_ising_energy(sp, L);
                     logr = -beta * D->J[0] * (double)(Ep - R->E) + (Fp - R->F);
                 } else {
-                    Sp = orc_kitaev_S(sp, C, L, D->J, beta, NULL, &Efp, &Cfp);
+                    Sp = orc_kitaev_S(sp, C, L, D->J, beta, epsp, &Efp, &Cfp);
                     logr = (Sp - R->S) + (Fp - R->F);
                 }
                 const double lu = log(orc_mh_uniform(D->seed, t, gid));
@@ -458,11 +481,19 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                 const int acc = D->target == 2 ? 1 : (lu < logr);
                 if (accept_log) accept_log[(size_t)g * n_sweeps + it] = (uint8_t)acc;
                 if (acc) {
+                    if (y) memcpy(y, s, (size_t)nv); /* the replica takes the old state */
                     memcpy(s, sp, (size_t)nv);
                     R->F = Fp;
                     if (D->target != 1) R->E = Ep;
-                    else { R->S = Sp; R->Ef = Efp; R->Cf = Cfp; }
+                    else {
+                        R->S = Sp;
+                        R->Ef = Efp;
+                        R->Cf = Cfp;
+                        if (eps) memcpy(eps + (size_t)g * n, epsp, sizeof(double) * (size_t)n);
+                    }
                     R->n_acc += 1;
+                } else if (y) {
+                    memcpy(y, sp, (size_t)nv); /* the replica keeps its Gibbs steps */
                 }
                 R->sweeps += 1;
                 if ((int64_t)t >= (int64_t)D->burnin) {
@@ -487,11 +518,84 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
         free(h);
         free(a);
         free(sp);
+        free(epsp);
     }
     if (ties) {
         ties[0] += gt;
         ties[1] += mt;
     }
+}
+
+/* One round of temperature swaps of parallel tempering (App. B, Eq.
+ * (acceptance) between two physical temperatures).  Chains form a grid
+ * g = rung * n_ladders + ladder; round r pairs rungs (q, q+1) for
+ * q = r % 2, r % 2 + 2, ... < n_rungs - 1.  For a pair (a, b):
+ *   Ising:  log A = J (beta_a - beta_b) (E_a - E_b)
+ *   Kitaev: log A = S_a(x_b) + S_b(x_a) - S_a(x_a) - S_b(x_b),
+ *           S_beta(x) = sum_lambda log 2cosh(beta eps_lambda(x) / 2)
+ * accept iff log u < log A (u from stream PT).  On acceptance the two
+ * physical states swap, with their cached E, F (and the singular values,
+ * recomputing S, Ef, Cf at the new temperatures); sums, replicas and sweep
+ * counters stay with the chain slot.  ties counts |log A - log u| < 1e-6. */
+ORC_API void orc_tempering_swap(const orc_run_desc* D, int C, const double* T, int8_t* state, orc_chain* rec,
+                                double* eps, int n_ladders, uint32_t round, int64_t* ties)
+{
+    const int L = D->L, n = L * L, nv = C * n;
+    const int n_rungs = D->n_chains / n_ladders;
+    int8_t* tmp = (int8_t*)malloc((size_t)nv);
+    double* etmp = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int q = (int)(round & 1u); q + 1 < n_rungs; q += 2) {
+        for (int l = 0; l < n_ladders; ++l) {
+            const int a = q * n_ladders + l, b = (q + 1) * n_ladders + l;
+            orc_chain *Ra = rec + a, *Rb = rec + b;
+            const double ba = 1.0 / T[a], bb = 1.0 / T[b];
+            double logA, Sab = 0, Sba = 0, Efab = 0, Efba = 0, Cfab = 0, Cfba = 0;
+            if (D->target != 1) {
+                logA = D->J[0] * (ba - bb) * (double)(Ra->E - Rb->E);
+            } else {
+                const double* ea = eps + (size_t)a * n;
+                const double* eb = eps + (size_t)b * n;
+                for (int i = 0; i < n; ++i) {
+                    const double xa = 0.5 * ba * eb[i], xb = 0.5 * bb * ea[i];
+                    Sab += log2cosh(xa);
+                    Sba += log2cosh(xb);
+                    Efab -= 0.5 * eb[i] * tanh(xa);
+                    Efba -= 0.5 * ea[i] * tanh(xb);
+                    Cfab += xa * xa / (cosh(xa) * cosh(xa));
+                    Cfba += xb * xb / (cosh(xb) * cosh(xb));
+                }
+                logA = Sab + Sba - Ra->S - Rb->S;
+            }
+            const double lu = log(orc_pt_uniform(D->seed, round, D->g0 + (uint32_t)a));
+            if (ties && fabs(logA - lu) < 1e-6) ++*ties;
+            if (!(lu < logA)) continue;
+            memcpy(tmp, state + (size_t)a * nv, (size_t)nv);
+            memcpy(state + (size_t)a * nv, state + (size_t)b * nv, (size_t)nv);
+            memcpy(state + (size_t)b * nv, tmp, (size_t)nv);
+            const double F = Ra->F;
+            Ra->F = Rb->F;
+            Rb->F = F;
+            if (D->target != 1) {
+                const int64_t E = Ra->E;
+                Ra->E = Rb->E;
+                Rb->E = E;
+            } else {
+                memcpy(etmp, eps + (size_t)a * n, sizeof(double) * (size_t)n);
+                memcpy(eps + (size_t)a * n, eps + (size_t)b * n, sizeof(double) * (size_t)n);
+                memcpy(eps + (size_t)b * n, etmp, sizeof(double) * (size_t)n);
+                Ra->S = Sab;
+                Ra->Ef = Efab;
+                Ra->Cf = Cfab;
+                Rb->S = Sba;
+                Rb->Ef = Efba;
+                Rb->Cf = Cfba;
+            }
+            Ra->n_swap += 1;
+            Rb->n_swap += 1;
+        }
+    }
+    free(tmp);
+    free(etmp);
 }
 
 /* ------------------------------------------------------------------ */
