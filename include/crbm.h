@@ -87,7 +87,19 @@ typedef struct {
 /* One job: n_chains chains on an L x L lattice.
  * T[g] > 0 is chain g's temperature.  Chain g uses the Philox chain index
  * chain_offset + g, so a chain's trajectory depends only on (seed, its index,
- * sweep number), never on how jobs are batched. */
+ * sweep number), never on how jobs are batched.
+ *
+ * rbm_state selects the form of the CRBM move (App. B):
+ *   NULL     - the CRBM replica is refreshed from the physical state before
+ *              every sweep: gibbs_k Gibbs steps from x give x', accepted with
+ *              the probability of Eq. (acceptance);
+ *   non-NULL - every chain keeps a persistent CRBM replica y (parallel
+ *              tempering with an exchange correction): each sweep advances y
+ *              by gibbs_k Gibbs steps to y' and exchanges it with x with the
+ *              same probability; accepted: x <- y', y <- x; rejected: y <- y'.
+ *              With init_state = 1 crbm_init copies the initial state into
+ *              rbm_state; otherwise the caller provides it.  Not allowed
+ *              with CRBM_GIBBS. */
 typedef struct {
     int32_t target;        /* crbm_target */
     int32_t L;             /* lattice side, 1 <= L <= 256 */
@@ -101,6 +113,7 @@ typedef struct {
     double J[3];           /* Ising: J[0] is J. Kitaev: J_x, J_y, J_z */
     const double* T;       /* device [n_chains] temperatures */
     int8_t* state;         /* device [n_chains][C][L][L], +-1, read and written */
+    int8_t* rbm_state;     /* device [n_chains][C][L][L] or NULL; see below */
     void* workspace;       /* device, >= crbm_workspace_size() bytes */
     size_t workspace_bytes;
 } crbm_batch_desc;
@@ -121,7 +134,9 @@ typedef struct {
     double Ef;            /* Kitaev fermion energy -sum eps/2 tanh(beta eps/2) */
     double Cf;            /* Kitaev sum (beta eps/2)^2 / cosh^2(beta eps/2) */
     double kE, kE2, kCf;  /* Kitaev sums of Ef, Ef^2, Cf */
-    double reserved[3];
+    double F_bound;       /* bound on |F - F_exact| of the cached F (0: exact FP64) */
+    int64_t n_swap;       /* accepted temperature swaps (crbm_tempering_swap) */
+    double reserved;
 } crbm_chain_stats;
 
 typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
@@ -143,6 +158,23 @@ CRBM_API crbm_status crbm_propose_accept(crbm_ctx* ctx, int32_t n_sweeps);
 /* Advance several jobs by n_sweeps each in shared launches (continuous
  * batching). All jobs must use the same stream. */
 CRBM_API crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps);
+
+/* One round of temperature swaps of parallel tempering (App. B, Eq.
+ * (acceptance) between two physical temperatures), stream-ordered after the
+ * job's sweeps.  The job's chains form a grid chain = rung * n_ladders +
+ * ladder (n_chains must be a multiple of n_ladders); round r pairs the rungs
+ * (q, q+1) for q = r % 2, r % 2 + 2, ... of every ladder.  For a pair (a, b):
+ *   Ising:  log A = J (1/T_a - 1/T_b) (E_a - E_b)
+ *   Kitaev: log A = S_a(x_b) + S_b(x_a) - S_a(x_a) - S_b(x_b), with
+ *           S_T(x) = sum_lambda log 2cosh(eps_lambda(x) / (2T)) from the
+ *           singular values kept in the workspace;
+ * the pair swaps its physical states iff log u < log A, u the 53-bit uniform
+ * of Philox counter (0, r, chain_offset + a, 4).  The cached E, F, F_bound
+ * (and singular values; S, Ef, Cf recomputed at the new temperatures) follow
+ * the states; sums, sweep counters and CRBM replicas stay with the chain;
+ * n_swap of both chains counts the swap.  Random numbers are indexed by r:
+ * use each round index once.  Not allowed with CRBM_GIBBS. */
+CRBM_API crbm_status crbm_tempering_swap(crbm_ctx* ctx, int32_t n_ladders, int32_t round);
 
 /* Copy the per-chain records, n_chains x crbm_chain_stats, to `out`
  * (device memory if on_device != 0, else host memory; the host copy

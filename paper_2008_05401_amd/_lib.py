@@ -31,7 +31,7 @@ class crbm_batch_desc(ct.Structure):
                 ("gibbs_k", ct.c_int32), ("burnin_sweeps", ct.c_int32), ("init_state", ct.c_int32),
                 ("chain_offset", ct.c_uint32), ("reserved", ct.c_int32), ("seed", ct.c_uint64),
                 ("J", ct.c_double * 3), ("T", ct.c_void_p), ("state", ct.c_void_p),
-                ("workspace", ct.c_void_p), ("workspace_bytes", ct.c_size_t)]
+                ("rbm_state", ct.c_void_p), ("workspace", ct.c_void_p), ("workspace_bytes", ct.c_size_t)]
 
 
 # crbm_chain_stats
@@ -39,11 +39,12 @@ STATS_DTYPE = np.dtype([
     ("sweeps", "<i8"), ("n_acc", "<i8"), ("n_meas", "<i8"), ("n_recheck", "<i8"),
     ("sumE", "<i8"), ("sumE2", "<i8"), ("sumM", "<i8"), ("sumAbsM", "<i8"), ("sumM2", "<i8"),
     ("E", "<i8"), ("F", "<f8"), ("S", "<f8"), ("Ef", "<f8"), ("Cf", "<f8"),
-    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"), ("reserved", "<f8", (3,)),
+    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"), ("F_bound", "<f8"), ("n_swap", "<i8"), ("reserved", "<f8"),
 ])
 assert STATS_DTYPE.itemsize == 160
 
 EXPORTS = ["crbm_workspace_size", "crbm_init", "crbm_propose_accept", "crbm_propose_accept_many",
+           "crbm_tempering_swap",
            "crbm_read_stats", "crbm_sweeps_done", "crbm_destroy", "crbm_free_energy", "target_energy",
            "crbm_grad_workspace_size", "crbm_grad", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
            "crbm_version"]
@@ -65,6 +66,7 @@ def load(path: str = LIB_PATH):
     L.crbm_init.argtypes = [P(vp), P(crbm_params), P(crbm_batch_desc), vp]
     L.crbm_propose_accept.argtypes = [vp, ct.c_int32]
     L.crbm_propose_accept_many.argtypes = [P(vp), ct.c_int32, ct.c_int32]
+    L.crbm_tempering_swap.argtypes = [vp, ct.c_int32, ct.c_int32]
     L.crbm_read_stats.argtypes = [vp, vp, ct.c_int32]
     L.crbm_sweeps_done.argtypes = [vp]
     L.crbm_sweeps_done.restype = ct.c_int64
@@ -80,7 +82,8 @@ def load(path: str = LIB_PATH):
     L.crbm_clear_tuning.restype = ct.c_int
     L.crbm_last_error.restype = ct.c_char_p
     L.crbm_version.restype = ct.c_char_p
-    for name in ("crbm_init", "crbm_propose_accept", "crbm_propose_accept_many", "crbm_read_stats",
+    for name in ("crbm_init", "crbm_propose_accept", "crbm_propose_accept_many", "crbm_tempering_swap",
+                 "crbm_read_stats",
                  "crbm_destroy", "crbm_free_energy", "target_energy", "crbm_grad"):
         getattr(L, name).restype = ct.c_int
     _lib = L
@@ -110,6 +113,10 @@ def crbm_propose_accept(ctx, n_sweeps: int):
 def crbm_propose_accept_many(ctxs, n_sweeps: int):
     arr = (ct.c_void_p * len(ctxs))(*ctxs)
     check(load().crbm_propose_accept_many(arr, len(ctxs), int(n_sweeps)))
+
+
+def crbm_tempering_swap(ctx, n_ladders: int, round_: int):
+    check(load().crbm_tempering_swap(ctx, int(n_ladders), int(round_)))
 
 
 def crbm_read_stats(ctx, out_ptr: int, on_device: bool):

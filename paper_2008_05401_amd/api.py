@@ -60,10 +60,17 @@ class CRBMParams:
 
 
 class Job:
-    """n independent chains of the CRBM-proposal + MH sampler, resident on the GPU."""
+    """n independent chains of the CRBM-proposal + MH sampler, resident on the GPU.
+
+    replica=True (or an explicit rbm_state) gives every chain a persistent CRBM
+    replica exchanged with the physical state each sweep (App. B exchange
+    correction); without it the replica is refreshed from the physical state.
+    tempering_swap() performs one round of temperature swaps on the ladder grid
+    chain = rung * n_ladders + ladder."""
 
     def __init__(self, params: CRBMParams, target: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
-                 burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, chain_offset: int = 0, stream=None):
+                 burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, chain_offset: int = 0, stream=None,
+                 replica: bool = False, rbm_state=None):
         dev = params.W.device
         self.params = params
         self.target = int(target)
@@ -80,11 +87,23 @@ class Job:
             self.state = st.to(device=dev, dtype=torch.int8).contiguous().clone()
             assert tuple(self.state.shape) == shape
             init = 0
+        self.rbm_state = None
+        if replica or rbm_state is not None:
+            if rbm_state is None:
+                # filled by crbm_init (copy of the initial state) or copied from `state`
+                self.rbm_state = (torch.empty(shape, dtype=torch.int8, device=dev) if init
+                                  else self.state.clone())
+            else:
+                rs = rbm_state if torch.is_tensor(rbm_state) else torch.from_numpy(
+                    np.ascontiguousarray(rbm_state, np.int8))
+                self.rbm_state = rs.to(device=dev, dtype=torch.int8).contiguous().clone()
+                assert tuple(self.rbm_state.shape) == shape
         self._p = params.struct()
         self._stream = stream
         self._desc = C.crbm_batch_desc(self.target, self.L, n, int(gibbs_k), int(burnin), init,
                                        int(chain_offset), 0, int(seed), (C.ct.c_double * 3)(*J),
-                                       self.T.data_ptr(), self.state.data_ptr(), 0, 0)
+                                       self.T.data_ptr(), self.state.data_ptr(),
+                                       self.rbm_state.data_ptr() if self.rbm_state is not None else None, 0, 0)
         ws = C.crbm_workspace_size(self._p, self._desc)
         if ws == 0:
             # let crbm_init produce the precise error message
@@ -98,6 +117,10 @@ class Job:
 
     def run(self, n_sweeps: int):
         C.crbm_propose_accept(self.ctx, int(n_sweeps))
+        return self
+
+    def tempering_swap(self, n_ladders: int, round_: int):
+        C.crbm_tempering_swap(self.ctx, int(n_ladders), int(round_))
         return self
 
     @property

@@ -95,6 +95,8 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
     if (d->target != CRBM_KITAEV && p->C != 1) return fail(CRBM_EINVAL, "Ising and Gibbs-only jobs need C=1 (got %d)", p->C);
     if (d->target == CRBM_KITAEV && d->L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", d->L);
+    if (d->target == CRBM_GIBBS && d->rbm_state)
+        return fail(CRBM_EINVAL, "a persistent CRBM replica needs a physical target (got CRBM_GIBBS)");
     Plan pl{};
     if (d->target != CRBM_KITAEV && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
@@ -115,7 +117,15 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-size_t workspace_bytes_for(int n_chains) { return round_up(kJobBytes + (size_t)n_chains * sizeof(ChainRec), 256); }
+// workspace: [job descriptor][one record per chain][Kitaev: singular values, n_chains x L^2 doubles]
+size_t records_end(int n_chains) { return round_up(kJobBytes + (size_t)n_chains * sizeof(ChainRec), 256); }
+
+size_t workspace_bytes_for(const crbm_batch_desc* d)
+{
+    size_t o = records_end(d->n_chains);
+    if (d->target == CRBM_KITAEV) o += round_up((size_t)d->n_chains * d->L * d->L * sizeof(double), 256);
+    return o;
+}
 
 }  // namespace
 
@@ -190,7 +200,7 @@ size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* des
 {
     Plan pl;
     if (plan_job(params, desc, &pl) != CRBM_OK) return 0;
-    return workspace_bytes_for(desc->n_chains);
+    return workspace_bytes_for(desc);
 }
 
 crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batch_desc* desc, void* stream)
@@ -201,7 +211,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     crbm_status st = plan_job(params, desc, &pl);
     if (st != CRBM_OK) return st;
     if (!desc->T || !desc->state || !desc->workspace) return fail(CRBM_EINVAL, "T, state and workspace must be device pointers");
-    const size_t need = workspace_bytes_for(desc->n_chains);
+    const size_t need = workspace_bytes_for(desc);
     if (desc->workspace_bytes < need)
         return fail(CRBM_EBUDGET, "workspace of %zu bytes, %zu needed", desc->workspace_bytes, need);
     if (((uintptr_t)desc->workspace & 255) != 0) return fail(CRBM_EINVAL, "workspace must be 256-byte aligned");
@@ -221,7 +231,9 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.vb = params->vbias;
     j.T = desc->T;
     j.state = desc->state;
+    j.rbm_state = desc->rbm_state;
     j.rec = c->rec;
+    j.eps = desc->target == CRBM_KITAEV ? (double*)((char*)desc->workspace + records_end(desc->n_chains)) : nullptr;
     j.J0 = desc->J[0];
     j.J1 = desc->J[1];
     j.J2 = desc->J[2];
@@ -288,6 +300,22 @@ crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32
     if (st == CRBM_OK)
         for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps += n_sweeps;
     return st;
+}
+
+crbm_status crbm_tempering_swap(crbm_ctx* ctx, int32_t n_ladders, int32_t round)
+{
+    if (!ctx) return fail(CRBM_EINVAL, "ctx is NULL");
+    if (ctx->desc.target == CRBM_GIBBS) return fail(CRBM_EINVAL, "temperature swaps need a physical target");
+    if (n_ladders < 1 || ctx->desc.n_chains % n_ladders != 0)
+        return fail(CRBM_EINVAL, "n_ladders=%d must divide n_chains=%d", n_ladders, ctx->desc.n_chains);
+    if (round < 0) return fail(CRBM_EINVAL, "round=%d must be >= 0", round);
+    const int n_rungs = ctx->desc.n_chains / n_ladders;
+    const int q0 = round & 1;
+    const int n_rung_pairs = n_rungs - q0 >= 2 ? (n_rungs - q0) / 2 : 0;
+    if (n_rung_pairs == 0) return CRBM_OK;
+    hipError_t e = launch_tempering_swap(ctx->job_dev, n_rung_pairs * n_ladders, n_ladders, q0, (uint32_t)round,
+                                         ctx->desc.target, ctx->stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "tempering swap launch");
 }
 
 crbm_status crbm_read_stats(crbm_ctx* ctx, crbm_chain_stats* out, int32_t on_device)

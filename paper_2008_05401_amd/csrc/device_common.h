@@ -48,19 +48,25 @@ __device__ __forceinline__ u32x4 philox10_uk(uint32_t c0, uint32_t c1, uint32_t 
     return philox10(c0, c1, c2, c3, k0, k1);
 }
 
-enum : uint32_t { STREAM_INIT = 0, STREAM_HID = 1, STREAM_VIS = 2, STREAM_MH = 3 };
+enum : uint32_t { STREAM_INIT = 0, STREAM_HID = 1, STREAM_VIS = 2, STREAM_MH = 3, STREAM_PT = 4 };
 
 __device__ __forceinline__ uint32_t word_of(const u32x4& r, int w)
 {
     return w == 0 ? r.x : (w == 1 ? r.y : (w == 2 ? r.z : r.w));
 }
 
-// 53-bit MH uniform of (chain, sweep): words 0,1 of unit group 0
-__device__ __forceinline__ double mh_uniform(uint64_t seed, uint32_t t, uint32_t g)
+// 53-bit uniform of (stream, index t, chain g): words 0,1 of unit group 0
+__device__ __forceinline__ double uniform53(uint64_t seed, uint32_t t, uint32_t g, uint32_t stream)
 {
-    const u32x4 r = philox10(0u, t, g, STREAM_MH, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const u32x4 r = philox10(0u, t, g, stream, (uint32_t)seed, (uint32_t)(seed >> 32));
     const uint64_t x = ((uint64_t)r.x << 32) | (uint64_t)r.y;
     return ((double)(x >> 11) + 0.5) * 0x1p-53;
+}
+
+// MH uniform of (chain, sweep)
+__device__ __forceinline__ double mh_uniform(uint64_t seed, uint32_t t, uint32_t g)
+{
+    return uniform53(seed, t, g, STREAM_MH);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +190,9 @@ struct ChainRec {
     long long E;
     double F, S, Ef, Cf;
     double kE, kE2, kCf;
-    double reserved[3];
+    double F_bound;     // bound on |F - F_exact| of the cached F
+    long long n_swap;   // accepted temperature swaps
+    double reserved;
 };
 static_assert(sizeof(ChainRec) == 160, "record layout");
 

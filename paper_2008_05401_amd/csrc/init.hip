@@ -48,10 +48,13 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     int8_t* state = J.state + (size_t)g * C * LL;
     if (J.init_state) {
+        // a persistent CRBM replica starts as a copy of the chain's state
+        int8_t* rbm = J.rbm_state ? J.rbm_state + (size_t)g * C * LL : nullptr;
         for (int q = tid; q < C * LL; q += NT) {
             const u32x4 r = philox10((uint32_t)q >> 2, 0u, gid, STREAM_INIT, k0, k1);
             const int8_t s = (word_of(r, q & 3) >> 31) ? (int8_t)1 : (int8_t)-1;
             state[q] = s;
+            if (rbm) rbm[q] = s;
             v[q] = s > 0;
         }
     } else {
@@ -68,7 +71,10 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
         double* A = kit;
         ko = kitaev_weight_block(v, C, L, J.J0, J.J1, J.J2, 1.0 / J.T[g], A, A + N * (N + 1) / 2,
                                  A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N, A + N * (N + 1) / 2 + 3 * N,
-                                 red);
+                                 red, A);
+        // singular values of the initial state, kept for temperature swaps
+        if (J.eps)
+            for (int q = tid; q < N; q += NT) J.eps[(size_t)g * N + q] = A[q];
     }
     if (tid == 0) {
         ChainRec R{};

@@ -30,7 +30,7 @@ struct KitaevOut {
 // v: 0/1 bytes of the proposal, C channels ([3][L][L] = x,y,z bonds, or [1][L][L] = z bonds).
 __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double Jx, double Jy, double Jz,
                                          double beta, double* A, double* d, double* e, double* hv, double* p,
-                                         double* red)
+                                         double* red, double* eps_out = nullptr)
 {
     const int N = L * L;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -176,6 +176,7 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
         }
         const double lam = 0.5 * (lo + hi);
         const double eps = sqrt(lam > 0.0 ? lam : 0.0);
+        if (eps_out) eps_out[idx] = eps;  // may alias A: A is dead after the tridiagonalisation
         const double x = 0.5 * beta * eps;
         S += log2cosh_d(x);
         Ef -= 0.5 * eps * tanh(x);

@@ -15,7 +15,9 @@ struct JobDev {
     const float* vb;
     const double* T;
     int8_t* state;
+    int8_t* rbm_state;  // persistent CRBM replicas or nullptr
     ChainRec* rec;
+    double* eps;        // Kitaev: singular values of every chain's current state [n_chains][L*L]
     double J0, J1, J2;
     uint64_t seed;
     int K, C, LW, target, L, n_chains, gibbs_k, burnin;
@@ -38,6 +40,8 @@ struct SweepLaunch {
 };
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target);
+hipError_t launch_tempering_swap(const JobDev* job_dev, int n_pairs, int n_ladders, int q0, uint32_t round,
+                                 int target, hipStream_t s);
 size_t init_lds(int K, int C, int LW, int L, int target);
 hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s);
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);

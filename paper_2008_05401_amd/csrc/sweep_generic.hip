@@ -101,9 +101,14 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     int8_t* state = J.state + (size_t)g * C * LL;
     ChainRec* rec = J.rec + g;
 
-    // load the state (crbm_init has generated it if asked to)
+    // load the state (crbm_init has generated it if asked to) into plane 0 and
+    // a persistent CRBM replica, if the job keeps one, into plane 1
+    const bool replica = J.rbm_state != nullptr;
+    int8_t* rbm_state = replica ? J.rbm_state + (size_t)g * C * LL : nullptr;
     uint8_t* vcur0 = vb3;
     for (int q = tid; q < C * LL; q += NT) vcur0[q] = state[q] > 0;
+    if (replica)
+        for (int q = tid; q < C * LL; q += NT) vb3[C * LL + q] = rbm_state[q] > 0;
     __syncthreads();
 
     const double T = J.T[g];
@@ -128,11 +133,11 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
         __syncthreads();
     }
     const uint32_t t0 = (uint32_t)sh_t0;
-    int cur = 0;
+    int cur = 0, rbm = 1;
     int nre = 0;
     for (int it = 0; it < P.n_sweeps; ++it) {
         const uint32_t t = t0 + (uint32_t)it;
-        int src = cur;
+        int src = replica ? rbm : cur;
         for (int sub = 0; sub < J.gibbs_k; ++sub) {
             int dst = (src + 1) % 3;
             if (dst == cur) dst = (dst + 1) % 3;
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             const int N = LL;
             ko = kitaev_weight_block(vp, C, L, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
                                      A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
-                                     A + N * (N + 1) / 2 + 3 * N, red);
+                                     A + N * (N + 1) / 2 + 3 * N, red, kit);
         }
         if (tid == 0) {
             const double logr = ising ? (-beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F)) : ((ko.S - R.S) + (Fp - R.F));
@@ -228,14 +233,25 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             }
         }
         __syncthreads();
+        // exchange: accepted -> x <- y', y <- x; rejected -> y <- y'
         if (sh_acc) {
+            rbm = cur;
             cur = src;
             Mcur = Mp;
+            if (!ising && J.eps)
+                for (int q = tid; q < LL; q += NT) J.eps[(size_t)g * LL + q] = kit[q];
+            __syncthreads();
+        } else {
+            rbm = src;
         }
     }
-    // store the state and the record
+    // store the state(s) and the record
     const uint8_t* vc = vb3 + cur * C * LL;
     for (int q = tid; q < C * LL; q += NT) state[q] = vc[q] ? (int8_t)1 : (int8_t)-1;
+    if (replica) {
+        const uint8_t* vr = vb3 + rbm * C * LL;
+        for (int q = tid; q < C * LL; q += NT) rbm_state[q] = vr[q] ? (int8_t)1 : (int8_t)-1;
+    }
     const int tot = block_sum(nre, (int*)redi);
     if (tid == 0) {
         R.n_recheck += tot;

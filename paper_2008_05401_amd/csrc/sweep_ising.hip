@@ -443,7 +443,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     __shared__ double sh_lu[LU_CHUNK];
     __shared__ double sh_dc[NDC];
     __shared__ long long sh_Mcur;
-    __shared__ int sh_cur;
+    __shared__ int sh_cur, sh_rbm;
     __shared__ double sh_Bchain;
 
     const float* __restrict__ W = J.W;
@@ -525,22 +525,42 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     int8_t* state = J.state + (size_t)g * L * L;
     ChainRec* rec = J.rec + g;
 
-    // load the state into plane 0 (4 int8 per lane; +1 = 0x01, -1 = 0xFF)
-    for (int r = 0; r < nrounds; ++r) {
-        const int Q = r * NT + tid;
-        const bool active = Q < nq;
-        const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
-        uint32_t nib = 0;
-        if (active) {
-            const uint32_t w4 = ~*(const uint32_t*)(state + (i << lgL) + 4 * m);
-            nib = ((w4 >> 7) & 1u) | ((w4 >> 14) & 2u) | ((w4 >> 21) & 4u) | ((w4 >> 28) & 8u);
+    // +-1 int8 lattice <-> bit plane (4 int8 per lane; +1 = 0x01, -1 = 0xFF)
+    auto load_plane = [&](const int8_t* src, uint32_t* pl) {
+        for (int r = 0; r < nrounds; ++r) {
+            const int Q = r * NT + tid;
+            const bool active = Q < nq;
+            const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+            uint32_t nib = 0;
+            if (active) {
+                const uint32_t w4 = ~*(const uint32_t*)(src + (i << lgL) + 4 * m);
+                nib = ((w4 >> 7) & 1u) | ((w4 >> 14) & 2u) | ((w4 >> 21) & 4u) | ((w4 >> 28) & 8u);
+            }
+            store_nibble(pl, RS, L, i, m, nib, active);
         }
-        store_nibble(vpl, RS, L, i, m, nib, active);
-    }
+    };
+    auto store_plane = [&](const uint32_t* pl, int8_t* dst) {
+        for (int r = 0; r < nrounds; ++r) {
+            const int Q = r * NT + tid;
+            if (Q < nq) {
+                const int i = Q >> lgq, m = Q & ((L >> 2) - 1);
+                const uint32_t nib = quad_bits(pl, RS, L, i, m);
+                const uint32_t up = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+                const uint32_t dn =
+                    ((~nib) & 1u) | (((~nib) & 2u) << 7) | (((~nib) & 4u) << 14) | (((~nib) & 8u) << 21);
+                *(uint32_t*)(dst + (i << lgL) + 4 * m) = up | (dn * 0xFFu);
+            }
+        }
+    };
+    // physical state in plane 0; a persistent CRBM replica in plane 1
+    const bool replica = J.rbm_state != nullptr;
+    int8_t* rbm_state = replica ? J.rbm_state + (size_t)g * L * L : nullptr;
+    load_plane(state, vpl);
+    if (replica) load_plane(rbm_state, vpl + PL);
     if (tid == 0) {
         R = *rec;
         sh_t0 = R.sweeps;
-        sh_Bcur = R.reserved[0];
+        sh_Bcur = R.F_bound;
     }
     __syncthreads();
     {
@@ -549,6 +569,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         if (tid == 0) {
             sh_Mcur = Mcur;
             sh_cur = 0;
+            sh_rbm = 1;
         }
     }
     const uint32_t t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_t0);
@@ -576,7 +597,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             if (tid < LU_CHUNK && it + tid < P.n_sweeps) sh_lu[tid] = log_c(mh_uniform(J.seed, t + (uint32_t)tid, gid), sh_dc);
             __syncthreads();
         }
-        int src = cur;
+        // the Gibbs chain starts from the replica (persistent) or the physical state
+        int src = replica ? __builtin_amdgcn_readfirstlane(sh_rbm) : cur;
         for (int sub = 0; sub < J.gibbs_k; ++sub) {
             int dst = src == 2 ? 0 : src + 1;
             if (dst == cur) dst = dst == 2 ? 0 : dst + 1;
@@ -893,26 +915,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                 R.sumM2 += mm * mm;
             }
         }
-        if (flag && tid == 0) {
-            sh_cur = src;
-            sh_Mcur = Mp;
+        if (tid == 0) {
+            // exchange: accepted -> x <- y', y <- x; rejected -> y <- y'
+            if (flag) {
+                sh_cur = src;
+                sh_Mcur = Mp;
+                sh_rbm = cur;
+            } else {
+                sh_rbm = src;
+            }
         }
         __syncthreads();
     }
-    const int cur = __builtin_amdgcn_readfirstlane(sh_cur);
-    // store the state
-    for (int r = 0; r < nrounds; ++r) {
-        const int Q = r * NT + tid;
-        if (Q < nq) {
-            const int i = Q >> lgq, m = Q & ((L >> 2) - 1);
-            const uint32_t nib = quad_bits(vpl + cur * PL, RS, L, i, m);
-            const uint32_t up = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
-            const uint32_t dn = ((~nib) & 1u) | (((~nib) & 2u) << 7) | (((~nib) & 4u) << 14) | (((~nib) & 8u) << 21);
-            *(uint32_t*)(state + (i << lgL) + 4 * m) = up | (dn * 0xFFu);
-        }
-    }
+    store_plane(vpl + __builtin_amdgcn_readfirstlane(sh_cur) * PL, state);
+    if (replica) store_plane(vpl + __builtin_amdgcn_readfirstlane(sh_rbm) * PL, rbm_state);
     if (tid == 0) {
-        R.reserved[0] = sh_Bcur;
+        R.F_bound = sh_Bcur;
         *rec = R;
     }
 }

@@ -48,10 +48,11 @@ def _params(K=4, C=1, Lw=3, ptr=0x1000):
     return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr)
 
 
-def _desc(target=0, L=8, n=4, gk=1):
+def _desc(target=0, L=8, n=4, gk=1, rbm=None):
     from paper_2008_05401_amd import _lib
-    return _lib.crbm_batch_desc(target, L, n, gk, 0, 1, 0, 0, 0, (ct.c_double * 3)(1, 1, 1),
-                                0x1000, 0x1000, 0x1000, 1 << 20)
+    return _lib.crbm_batch_desc(target=target, L=L, n_chains=n, gibbs_k=gk, burnin_sweeps=0, init_state=1,
+                                chain_offset=0, reserved=0, seed=0, J=(ct.c_double * 3)(1, 1, 1), T=0x1000,
+                                state=0x1000, rbm_state=rbm, workspace=0x1000, workspace_bytes=1 << 20)
 
 
 def test_workspace_size_validation(lib):
@@ -66,6 +67,11 @@ def test_workspace_size_validation(lib):
     assert _lib.crbm_workspace_size(_params(), _desc(gk=0)) == 0
     assert _lib.crbm_workspace_size(_params(), _desc(L=257)) == 0
     assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=13)) == 0
+    assert _lib.crbm_workspace_size(_params(), _desc(target=2, rbm=0x1000)) == 0  # replica needs a target
+    assert _lib.crbm_workspace_size(_params(), _desc(rbm=0x1000)) > 0
+    # Kitaev keeps the singular values of every chain: 4 chains x 36 doubles more
+    kit = _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=6))
+    assert kit >= _lib.crbm_workspace_size(_params(), _desc(L=6)) + 4 * 36 * 8
 
 
 def test_init_rejects_before_device_work(lib):
@@ -96,9 +102,11 @@ def test_other_entry_points_validate(lib):
     assert L.crbm_grad(ct.byref(p), 0x1000, 1, 8, 0x1000, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EBUDGET
     assert L.crbm_propose_accept(None, 1) == _lib.CRBM_EINVAL
     assert L.crbm_propose_accept_many(None, 1, 1) == _lib.CRBM_EINVAL
+    assert L.crbm_tempering_swap(None, 1, 0) == _lib.CRBM_EINVAL
 
 
 def test_stats_record_layout(lib):
     _lib, _ = lib
     assert _lib.STATS_DTYPE.itemsize == 160
     assert np.dtype(_lib.STATS_DTYPE).names[:4] == ("sweeps", "n_acc", "n_meas", "n_recheck")
+    assert _lib.STATS_DTYPE.fields["F_bound"][1] == 136 and _lib.STATS_DTYPE.fields["n_swap"][1] == 144

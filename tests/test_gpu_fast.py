@@ -30,9 +30,9 @@ def check_chains(orc, job, ch, f_atol):
     assert np.array_equal(job.state.cpu().numpy(), ch.state)
     for name in ("sweeps", "n_acc", "n_meas", "E", "sumE", "sumE2", "sumM", "sumAbsM", "sumM2"):
         assert np.array_equal(st[name], ch.rec[name]), name
-    # F of the current state: float32-term sum within its rigorous bound (reserved[0])
+    # F of the current state: float32-term sum within its rigorous bound (F_bound)
     # (FP64 sums in a different order agree to ~1e-13 relative)
-    bound = st["reserved"][:, 0]
+    bound = st["F_bound"]
     tol = bound + f_atol + 1e-11 * np.abs(ch.rec["F"])
     assert np.all(np.abs(st["F"] - ch.rec["F"]) <= tol), np.abs(st["F"] - ch.rec["F"]).max()
     assert ch.ties[0] == 0 and ch.ties[1] == 0
@@ -182,7 +182,7 @@ def test_tile_shapes_give_identical_chains(orc, api, L):
                 for name in ("n_acc", "E", "sumE", "sumE2", "sumM", "sumAbsM", "sumM2"):
                     assert np.array_equal(st[name], ref[1][name]), (rows, nt, name)
                 # F: float32 terms grouped per lane block, so equal only within the two bounds
-                tol = st["reserved"][:, 0] + ref[1]["reserved"][:, 0] + 1e-11 * np.abs(st["F"])
+                tol = st["F_bound"] + ref[1]["F_bound"] + 1e-11 * np.abs(st["F"])
                 assert np.all(np.abs(st["F"] - ref[1]["F"]) <= tol), (rows, nt)
     finally:
         api.clear_tuning()

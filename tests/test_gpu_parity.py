@@ -47,8 +47,8 @@ def _compare_records(gpu, ora, target, f_rtol=1e-9):
         for name in ("S", "Ef", "Cf", "kE", "kE2", "kCf"):
             np.testing.assert_allclose(gpu[name], ora[name], rtol=1e-8, atol=1e-8, err_msg=name)
     # F: FP64 on the generic path; on the bit-packed Ising path a float32-term sum whose
-    # rigorous error bound is kept in reserved[0]; both far inside the 1e-5 relative bar
-    tol = gpu["reserved"][:, 0] + f_rtol * (1.0 + np.abs(ora["F"]))
+    # rigorous error bound is kept in F_bound; both far inside the 1e-5 relative bar
+    tol = gpu["F_bound"] + f_rtol * (1.0 + np.abs(ora["F"]))
     assert np.all(np.abs(gpu["F"] - ora["F"]) <= tol), np.abs(gpu["F"] - ora["F"]).max()
     assert np.all(np.abs(gpu["F"] - ora["F"]) <= 1e-5 * np.abs(ora["F"]) + 1e-9)
 
