@@ -40,9 +40,9 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 # after any change to them `traffic` is reported as null until re-measured.
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
                   "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": "32845f392c8fefd08dc36ea1917497c485e4f8cb85796b6b26be899ee8f27f56",
+MEASURED_TRAFFIC = {"sources_sha256": "f27edc46d677e33794d33d6d8dfbe8a1e79902a86eeeaa539663240e10f0299e",
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
-                    "fetch_kib": 9343.2, "fetch_scale": 2.0, "write_kib": 21156.3, "write_scale": 1.0}
+                    "fetch_kib": 9340.9, "fetch_scale": 2.0, "write_kib": 21152.5, "write_scale": 1.0}
 
 
 def kernel_sources_sha256():
@@ -168,6 +168,47 @@ def kitaev(sweeps6=20, sweeps12=2):
             "ms_per_sweep": ms, "mh_steps_per_s": n / (ms * 1e-3),
             "eigen_flops_per_sweep": n * (4.0 / 3.0) * N ** 3,
             "acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
+    return out
+
+
+def tempering(blocks=20, block_sweeps=5):
+    """Parallel tempering with the exchange correction (App. B): the batched
+    Ising config (4096 chains, L=64, K=8 5x5 ~ N(0,0.05), 32 rungs
+    linspace(1.5, 3.5) x 128 ladders) with persistent CRBM replicas, one swap
+    round after every block of sweeps; and Kitaev L=6 (K=8 3x3 ~ N(0,0.1),
+    16 rungs geomspace(0.005, 0.05) x 16 ladders).  Reported: throughput of the
+    whole cycle, swap acceptance, time of one swap round."""
+    import torch
+
+    from paper_2008_05401_amd import api, workloads as WL
+    out = {}
+    cases = (("ising_L64_4096", api.ISING, 64, WL.random_filters(8, 1, 5, 0.05, seed=0),
+              WL.ising_temperatures_linspace(32, 1.5, 3.5, 4096), 128, block_sweeps, blocks),
+             ("kitaev_L6_256", api.KITAEV, 6, WL.random_filters(8, 3, 3, 0.1, seed=0),
+              np.repeat(np.geomspace(0.005, 0.05, 16), 16), 16, 1, 10))
+    for name, target, L, f, T, nl, bs, nb in cases:
+        job = api.Job(api.CRBMParams.from_filters(f), target, L, T, seed=0, replica=True)
+        job.run(bs)
+        job.tempering_swap(nl, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(nb):
+            job.run(bs)
+            job.tempering_swap(nl, 1 + b)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = job.stats()
+        swap_ms = _timed(lambda: job.tempering_swap(nl, 10 ** 6), reps=1)
+        n = len(T)
+        rungs = n // nl
+        pairs = sum(((rungs - (r % 2)) // 2) * nl for r in range(1, nb + 1))
+        out[name] = {
+            "chains": n, "ladders": nl, "rungs": rungs, "sweeps_per_swap_round": bs,
+            "site_sweeps_per_s": n * L * L * bs * nb / wall if target == api.ISING else None,
+            "mh_steps_per_s": n * bs * nb / wall,
+            "exchange_acceptance": float(st["n_acc"].sum() / st["sweeps"].sum()),
+            "swap_acceptance": float(st["n_swap"].sum() / 2 / max(1, pairs + ((rungs // 2) * nl))),
+            "swap_round_ms": swap_ms}
     return out
 
 
@@ -330,6 +371,7 @@ def main():
                   "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds_tbs / PEAK_LDS_TBS}
     if not args.no_extra:
         out["kitaev"] = kitaev()
+        out["tempering"] = tempering()
         out["training"] = training_and_transfer()
     if not args.no_served:
         del job
