@@ -247,6 +247,40 @@ def training_and_transfer(epochs=20, lr=1e-2):
         "transfer_acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
 
 
+def kitaev_training_and_transfer(L=6, L_big=12, T=0.3):
+    """Sec. IV: a Kitaev CRBM (K=8, C=3, 3x3) pre-trained on random gauge
+    configurations at L=6, finished on samples it drew itself (persistent
+    replicas), then used at L=12 (128 chains): exchange acceptance of the
+    initial, pre-trained and trained filters with the refreshed replica."""
+    import torch
+
+    from paper_2008_05401_amd import api, train, workloads as WL
+    t0 = time.perf_counter()
+    pre, fin, x, acc_self, xr = train.kitaev_pretrain_and_train(L, T, n_random=4096, n_phys=512, pre_epochs=10,
+                                                                epochs=10, sweeps=200, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    f0 = WL.alg1_init_filters(8, 3, seed=0, C=3)
+    nlp = train.kitaev_nlp(T)
+    z8, z3 = torch.zeros(8, device="cuda"), torch.zeros(3, device="cuda")
+    W0 = torch.tensor(f0.W, device="cuda")
+    nx, nr = nlp(x), nlp(xr)
+    out = {"L_train": L, "T": T, "train_s": train_s, "self_sample_acceptance": acc_self,
+           "loss_random_states": {"initial": train.full_loss_nlp(xr, nr, W0, z8, z3),
+                                  "pretrained": train.full_loss_nlp(xr, nr, pre.W, pre.hbias, pre.vbias)},
+           "loss_self_samples": {"initial": train.full_loss_nlp(x, nx, W0, z8, z3),
+                                 "pretrained": train.full_loss_nlp(x, nx, pre.W, pre.hbias, pre.vbias),
+                                 "trained": train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)}}
+    for name, (W, hb, vb) in (("initial", (f0.W, f0.hbias, f0.vbias)), ("pretrained", (pre.W, pre.hbias, pre.vbias)),
+                              ("trained", (fin.W, fin.hbias, fin.vbias))):
+        job = api.Job(api.CRBMParams(W, hb, vb), api.KITAEV, L_big, np.full(128, T), seed=5)
+        job.run(4)
+        st = job.stats()
+        out[f"acceptance_L{L_big}_{name}"] = float(st["n_acc"].sum() / st["sweeps"].sum())
+        job.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,6 +407,7 @@ def main():
         out["kitaev"] = kitaev()
         out["tempering"] = tempering()
         out["training"] = training_and_transfer()
+        out["kitaev_training"] = kitaev_training_and_transfer()
     if not args.no_served:
         del job
         out["served"] = served(args.served_jobs, args.served_rate, args.served_warmup, args.served_sweeps,

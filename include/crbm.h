@@ -71,8 +71,8 @@ typedef enum {
 
 /* CRBM_GIBBS: no target; every proposal is accepted, so the chain is the plain
  * block-Gibbs chain of the CRBM (App. B) -- the sampler of the replay buffer of
- * Alg. 1 and the "uncorrected" RBM of App. B.  Needs C = 1; the Ising
- * observables of the states are still accumulated. */
+ * Alg. 1 and the "uncorrected" RBM of App. B.  C = 1 or 3; the Ising
+ * observables of channel 0 are still accumulated. */
 typedef enum { CRBM_ISING = 0, CRBM_KITAEV = 1, CRBM_GIBBS = 2 } crbm_target;
 
 /* CRBM parameters theta = (W, hbias, vbias); all device, float32.

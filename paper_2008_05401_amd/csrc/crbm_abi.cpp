@@ -93,12 +93,12 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->n_chains < 1) return fail(CRBM_EINVAL, "n_chains=%d must be >= 1", d->n_chains);
     if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
-    if (d->target != CRBM_KITAEV && p->C != 1) return fail(CRBM_EINVAL, "Ising and Gibbs-only jobs need C=1 (got %d)", p->C);
+    if (d->target == CRBM_ISING && p->C != 1) return fail(CRBM_EINVAL, "Ising jobs need C=1 (got %d)", p->C);
     if (d->target == CRBM_KITAEV && d->L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", d->L);
     if (d->target == CRBM_GIBBS && d->rbm_state)
         return fail(CRBM_EINVAL, "a persistent CRBM replica needs a physical target (got CRBM_GIBBS)");
     Plan pl{};
-    if (d->target != CRBM_KITAEV && ising_fast_supported(p->K, p->Lw, d->L)) {
+    if (d->target != CRBM_KITAEV && p->C == 1 && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
         pl.nt = ising_fast_threads(d->L);
         pl.rows = ising_fast_rows(d->L);
@@ -107,6 +107,8 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     } else {
         pl.kernel = K_GENERIC;
         pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
+        // the Kitaev eigen-step is latency-bound: one 16-wave workgroup per chain from N = 16 on
+        if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = 1024;
         pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target);
     }
     if (pl.lds > kLdsLimit)

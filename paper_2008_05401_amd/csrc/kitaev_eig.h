@@ -7,8 +7,8 @@
 //      site has three black neighbours, so A has at most 7 non-zeros per row);
 //      A is held in LDS as a packed lower triangle (N(N+1)/2 doubles);
 //   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e);
-//   3. every eigenvalue lambda_i of the tridiagonal matrix by bisection on the
-//      Sturm count, one thread per eigenvalue;
+//   3. every eigenvalue lambda_i of the tridiagonal matrix by trisection on
+//      the Sturm count (division-free recurrence), one thread per eigenvalue;
 //   4. eps_i = sqrt(max(lambda_i, 0)); S, the fermion energy and the
 //      fluctuation term are reduced over the workgroup.
 // Eigenvalues of A are accurate to ~N * 2^-52 * |A| in absolute terms; since
@@ -83,14 +83,35 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
     }
     __syncthreads();
 
-    // 2. Householder tridiagonalisation of the packed symmetric A
+    // 2. Householder tridiagonalisation of the packed symmetric A.  Per step k:
+    //    v from column k, p = bet A22 v with G = 16 lanes per row (two
+    //    accumulators each, swizzle-reduced), then
+    //    A22 -= v w^T + w v^T with w = p - kk v, kk = (bet/2)(p.v), i.e.
+    //    A22 -= v p^T + p v^T - 2 kk v v^T, one wave per row, lanes along it.
+    //    Five barriers per step: the two reductions alternate between two LDS
+    //    slots, so a slot is never rewritten while another wave still reads it.
+    //    nt is a multiple of 64.
+    constexpr int G = 16;
+    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+    const int grp = tid / G, gl = tid - (tid / G) * G, ngrp = nt / G;
+    int slot = 0;
+    auto reduce = [&](double x) -> double {
+        x = wave_sum(x);
+        double* r = red + 16 * slot;  // 16 waves at most
+        slot ^= 1;
+        if (lane == 0) r[wid] = x;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += r[w];
+        return t;
+    };
     for (int k = 0; k + 2 < N; ++k) {
         double s2 = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) {
             const double x = A[tri(i, k)];
             s2 += x * x;
         }
-        s2 = block_sum(s2, red);
+        s2 = reduce(s2);
         const double x0 = A[tri(k + 1, k)];
         const double rest = s2 - x0 * x0;
         if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
@@ -104,31 +125,54 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
         const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
         for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : A[tri(i, k)];
         __syncthreads();
-        // p = bet * A22 v
-        for (int i = k + 1 + tid; i < N; i += nt) {
-            double acc = 0.0;
-            for (int j = k + 1; j <= i; ++j) acc += A[tri(i, j)] * hv[j];
-            for (int j = i + 1; j < N; ++j) acc += A[tri(j, i)] * hv[j];
-            p[i] = bet * acc;
+        // p = bet * A22 v; row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
+        for (int i = k + 1 + grp; i < N; i += ngrp) {
+            const int rb = tri(i, 0);
+            double a0 = 0.0, a1 = 0.0;
+            int j = k + 1 + gl;
+            for (; j + G <= i; j += 2 * G) {
+                a0 += A[rb + j] * hv[j];
+                a1 += A[rb + j + G] * hv[j + G];
+            }
+            if (j <= i) a0 += A[rb + j] * hv[j];
+            j = i + 1 + gl;
+            for (; j + G < N; j += 2 * G) {
+                a0 += A[tri(j, i)] * hv[j];
+                a1 += A[tri(j + G, i)] * hv[j + G];
+            }
+            if (j < N) a0 += A[tri(j, i)] * hv[j];
+            double acc = a0 + a1;
+            acc += swz_xor<8>(acc);
+            acc += swz_xor<4>(acc);
+            acc += swz_xor<2>(acc);
+            acc += swz_xor<1>(acc);
+            if (gl == 0) p[i] = bet * acc;
         }
         __syncthreads();
         double pv = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) pv += p[i] * hv[i];
-        pv = block_sum(pv, red);
-        const double kk = 0.5 * bet * pv;
-        for (int i = k + 1 + tid; i < N; i += nt) p[i] -= kk * hv[i];  // p := w
-        __syncthreads();
-        // A22 -= v w^T + w v^T (lower triangle)
-        const int m = N - k - 1;
-        const int cnt = m * (m + 1) / 2;
-        for (int idx = tid; idx < cnt; idx += nt) {
-            // invert idx -> (ii, jj) with jj <= ii inside the trailing block
-            int ii = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-            while ((ii + 1) * (ii + 2) / 2 <= idx) ++ii;
-            while (ii * (ii + 1) / 2 > idx) --ii;
-            const int jj = idx - ii * (ii + 1) / 2;
-            const int gi = ii + k + 1, gj = jj + k + 1;
-            A[tri(gi, gj)] -= hv[gi] * p[gj] + p[gi] * hv[gj];
+        const double kk2 = bet * reduce(pv);  // 2 kk
+        // A22 -= v p^T + p v^T - 2 kk v v^T (lower triangle); a lane keeps the
+        // column values p_j, v_j of its (at most three) columns in registers
+        // (N <= 192; the callers allow L <= 12, N <= 144)
+        {
+            double pj[3], vj[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int j = k + 1 + lane + 64 * c;
+                pj[c] = j < N ? p[j] : 0.0;
+                vj[c] = j < N ? hv[j] : 0.0;
+            }
+            for (int i = k + 1 + wid; i < N; i += nw) {
+                const int rb = tri(i, 0);
+                const double vi = hv[i], pi = p[i];
+                const double ci = pi - kk2 * vi;  // p_i - 2 kk v_i
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int j = k + 1 + lane + 64 * c;
+                    if (j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
+                }
+            }
         }
         if (tid == 0) {
             d[k] = A[tri(k, k)];
@@ -144,44 +188,94 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
         d[N - 1] = A[tri(N - 1, N - 1)];
     }
     __syncthreads();
+    double* ee = hv;  // e^2, hv is free now
+    for (int i = tid; i + 1 < N; i += nt) ee[i] = e[i] * e[i];
+    __syncthreads();
 
-    // 3. bisection, one thread per eigenvalue
+    // 3. eigenvalue idx of the tridiagonal matrix, one lane per eigenvalue, by
+    //    trisection on the Sturm count: two interior points per step give two
+    //    independent recurrences per lane (the step is latency-bound) and cut
+    //    the bracket three-fold.  The count comes from the division-free
+    //    three-term recurrence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2},
+    //    p_i = det(T_i - x), one eigenvalue below x per sign change of
+    //    p_i / p_{i-1}; an exact zero is replaced by -2^-100 p_{i-1} (the sign
+    //    convention of the ratio form), and the pair is rescaled by 2^-+100
+    //    every eight steps to stay in range.  Within a lane the operands of
+    //    eight steps are read from LDS before the eight dependent steps.
+    double glo = 0.0, ghi = 0.0;  // Gershgorin bracket of the whole spectrum
+    for (int i = 0; i < N; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+        glo = fmin(glo, d[i] - r);
+        ghi = fmax(ghi, d[i] + r);
+    }
+    const double scale = fmax(fabs(glo), fabs(ghi));
+    const double tol = 4e-16 * scale + 1e-300;
     double S = 0.0, Ef = 0.0, Cf = 0.0;
     for (int idx = tid; idx < N; idx += nt) {
-        double lo = 0.0, hi = 0.0;
-        for (int i = 0; i < N; ++i) {
-            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-            lo = fmin(lo, d[i] - r);
-            hi = fmax(hi, d[i] + r);
-        }
-        const double scale = fmax(fabs(lo), fabs(hi));
-        const double pivmin = 1e-290 * fmax(1.0, scale * scale);
-        lo -= 1e-14 * scale + 1e-300;
-        hi += 1e-14 * scale + 1e-300;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (!(hi - lo > 4e-16 * scale + pivmin) || mid == lo || mid == hi) break;
-            // number of eigenvalues < mid
-            int count = 0;
-            double q = d[0] - mid;
-            if (fabs(q) < pivmin) q = -pivmin;
-            count += q < 0.0;
-            for (int i = 1; i < N; ++i) {
-                q = d[i] - mid - e[i - 1] * e[i - 1] / q;
-                if (fabs(q) < pivmin) q = -pivmin;
-                count += q < 0.0;
+        double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
+        for (int it = 0; it < 96; ++it) {
+            if (!(hi - lo > tol)) break;
+            const double h = (hi - lo) * (1.0 / 3.0);
+            const double xa = lo + h, xb = hi - h;
+            if (!(xa > lo && xb < hi && xa < xb)) break;  // no representable progress
+            double pa0 = 1.0, pa1 = d[0] - xa, pb0 = 1.0, pb1 = d[0] - xb;
+            if (pa1 == 0.0) pa1 = -0x1p-100;
+            if (pb1 == 0.0) pb1 = -0x1p-100;
+            int ca = pa1 < 0.0, cb = pb1 < 0.0;
+            // one step of both recurrences
+            auto step = [&](double di, double e2) {
+                double pa = fma(di - xa, pa1, -e2 * pa0);
+                double pb = fma(di - xb, pb1, -e2 * pb0);
+                if (pa == 0.0) pa = -0x1p-100 * pa1;
+                if (pb == 0.0) pb = -0x1p-100 * pb1;
+                ca += (pa < 0.0) != (pa1 < 0.0);
+                cb += (pb < 0.0) != (pb1 < 0.0);
+                pa0 = pa1;
+                pa1 = pa;
+                pb0 = pb1;
+                pb1 = pb;
+            };
+            auto rescale = [&]() {
+                const double fa = fabs(pa1) > 0x1p+100 ? 0x1p-100 : (fabs(pa1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                const double fb = fabs(pb1) > 0x1p+100 ? 0x1p-100 : (fabs(pb1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                pa0 *= fa;
+                pa1 *= fa;
+                pb0 *= fb;
+                pb1 *= fb;
+            };
+            // the first (N - 1) % 8 steps one by one, then blocks of eight whose
+            // operands are loaded together ahead of the recurrences
+            const int r0 = (N - 1) & 7;
+            for (int i = 1; i <= r0; ++i) step(d[i], ee[i - 1]);
+            rescale();
+            for (int i0 = r0 + 1; i0 < N; i0 += 8) {
+                double dv[8], ev[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    dv[u] = d[i0 + u];
+                    ev[u] = ee[i0 + u - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) step(dv[u], ev[u]);
+                rescale();
             }
-            if (count > idx) hi = mid;
-            else lo = mid;
+            // eigenvalue idx lies below x iff more than idx eigenvalues do
+            if (ca > idx) hi = xa;
+            else if (cb > idx) {
+                lo = xa;
+                hi = xb;
+            } else {
+                lo = xb;
+            }
         }
         const double lam = 0.5 * (lo + hi);
         const double eps = sqrt(lam > 0.0 ? lam : 0.0);
         if (eps_out) eps_out[idx] = eps;  // may alias A: A is dead after the tridiagonalisation
-        const double x = 0.5 * beta * eps;
-        S += log2cosh_d(x);
-        Ef -= 0.5 * eps * tanh(x);
-        const double ch = cosh(x);
-        Cf += (x * x) / (ch * ch);
+        const double xv = 0.5 * beta * eps;
+        S += log2cosh_d(xv);
+        Ef -= 0.5 * eps * tanh(xv);
+        const double ch = cosh(xv);
+        Cf += (xv * xv) / (ch * ch);
     }
     KitaevOut o;
     o.S = block_sum(S, red);

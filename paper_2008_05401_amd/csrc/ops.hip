@@ -86,7 +86,7 @@ hipError_t launch_ising_energy(const int8_t* x, int B, int L, int32_t* E, hipStr
 // ---------------------------------------------------------------------------
 // Kitaev S = sum log 2cosh(eps / 2T), FP64; one workgroup per configuration.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, double Jx,
+__global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, double Jx,
                                                             double Jy, double Jz, const double* __restrict__ T,
                                                             double* __restrict__ S)
 {
@@ -109,7 +109,8 @@ size_t kitaev_weight_lds(int C, int L) { return 64 * 8 + kitaev_lds_bytes(L) + (
 hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, double Jx, double Jy, double Jz, const double* T,
                                 double* S, hipStream_t s)
 {
-    hipLaunchKernelGGL(kitaev_weight_kernel, dim3(B), dim3(256), kitaev_weight_lds(C, L), s, x, C, L, Jx, Jy, Jz, T, S);
+    hipLaunchKernelGGL(kitaev_weight_kernel, dim3(B), dim3(L * L >= 16 ? 1024 : 256), kitaev_weight_lds(C, L), s, x, C, L,
+                       Jx, Jy, Jz, T, S);
     return hipGetLastError();
 }
 

@@ -113,14 +113,14 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 
     const double T = J.T[g];
     const double beta = 1.0 / T;
-    const bool ising = J.target != 1;      // Ising or Gibbs-only (C = 1)
+    const bool ising = J.target != 1;      // Ising or Gibbs-only (sums of channel 0)
     const bool gibbs_only = J.target == 2;
 
     // ---------------------------------------------------------------- sweeps
     __shared__ long long sh_t0;
     __shared__ int sh_acc;
     __shared__ long long sh_M;
-    ChainRec R;
+    __shared__ ChainRec R;  // touched by thread 0 only; in LDS so that no lane holds it in registers
     if (tid == 0) {
         R = *rec;
         sh_t0 = R.sweeps;
@@ -259,6 +259,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     }
 }
 
+template __global__ void sweep_generic_kernel<1024>(SweepLaunch);
 template __global__ void sweep_generic_kernel<256>(SweepLaunch);
 template __global__ void sweep_generic_kernel<64>(SweepLaunch);
 
@@ -271,6 +272,8 @@ hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt
 {
     if (nt == 64) {
         hipLaunchKernelGGL(sweep_generic_kernel<64>, dim3(n_blocks), dim3(64), lds, s, P);
+    } else if (nt == 1024) {
+        hipLaunchKernelGGL(sweep_generic_kernel<1024>, dim3(n_blocks), dim3(1024), lds, s, P);
     } else {
         hipLaunchKernelGGL(sweep_generic_kernel<256>, dim3(n_blocks), dim3(256), lds, s, P);
     }

@@ -1,17 +1,23 @@
-"""Training of a CRBM on Ising samples (Alg. 1 "Train the RBM") and transfer to
-a larger lattice, on the GPU.
+"""Training of a CRBM (Alg. 1 "Train the RBM") and transfer to a larger
+lattice, on the GPU, for the Ising and the Kitaev targets.
 
-* Physical training states: independent chains of the exact sampler (the
-  App. C kernel of the target temperature plus the MH correction), so no
-  local Metropolis run is needed (Sec. III notes the same for the Ising case).
+* Loss of Eq. (loss) with the optimal constant C(W): for a minibatch,
+  diff_i = nlp(x_i) - F(x_i) with nlp = -log P_phys up to a constant
+  (beta E for Ising, -S for Kitaev), C = mean(diff), loss = mean((diff - C)^2),
+  minimised with ADAM; F and its gradient run in the HIP kernels through
+  `api.CRBMFreeEnergy` (forward `crbm_free_energy`, backward `crbm_grad`).
 * Parameters initialised as in Alg. 1: W ~ N(0, 2/(K Lw^2)), biases 0.
 * Replay buffer of RBM samples (Alg. 1): `ub` new states per epoch from plain
   block-Gibbs chains of the current CRBM (target CRBM_GIBBS), the oldest
-  states dropped beyond the train size.
-* Loss of Eq. (loss) with the optimal constant C(W): for a minibatch,
-  diff_i = beta E(x_i) - F(x_i), C = mean(diff), loss = mean((diff - C)^2),
-  minimised with ADAM; F and its gradient run in the HIP kernels through
-  `api.CRBMFreeEnergy` (forward `crbm_free_energy`, backward `crbm_grad`).
+  states dropped beyond the train size; their nlp is evaluated on the GPU.
+* Physical training states:
+  - Ising: independent chains of the exact sampler (the App. C kernel of the
+    target temperature plus the MH correction), so no local Metropolis run is
+    needed (Sec. III notes the same for the Ising case);
+  - Kitaev (Sec. IV, pre-training): the CRBM is first trained on uniformly
+    random gauge configurations with their exact weights, then samples of the
+    physical distribution are drawn with the pre-trained CRBM through the
+    exchange-corrected sampler and the training is finished on them.
 """
 from __future__ import annotations
 
@@ -40,6 +46,16 @@ def exact_ising_samples(L: int, T: float, n: int, sweeps: int = 1000, seed: int 
     return x, E, float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
 
 
+def ising_nlp(T: float):
+    """-log P of the Ising model at T up to a constant: beta E (J = 1)."""
+    return lambda x: api.ising_energy(x).to(torch.float64) / T
+
+
+def kitaev_nlp(T: float, J=(1.0, 1.0, 1.0)):
+    """-log P of the Kitaev gauge field at T up to a constant: -S."""
+    return lambda x: -api.kitaev_weight(x, np.full(int(x.shape[0]), T), J)
+
+
 @dataclass
 class TrainResult:
     W: torch.Tensor
@@ -49,44 +65,57 @@ class TrainResult:
     steps: int
 
 
-def train(x_phys: torch.Tensor, E_phys: torch.Tensor, T: float, K: int = 8, Lw: int = 5, epochs: int = 30,
-          batch: int = 20, lr: float = 1e-3, ub: int = 200, gibbs_k: int = 1, seed: int = 0,
-          train_size: int = None, log_every: int = 0) -> TrainResult:
+def _params_of(f, dev):
+    return (torch.tensor(f.W, device=dev, requires_grad=True), torch.tensor(f.hbias, device=dev, requires_grad=True),
+            torch.tensor(f.vbias, device=dev, requires_grad=True))
+
+
+def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K: int = 8, Lw: int = 5,
+               epochs: int = 30, batch: int = 20, lr: float = 1e-3, ub: int = 200, gibbs_k: int = 1, seed: int = 0,
+               train_size: int = None, log_every: int = 0, init=None, replay: bool = True) -> TrainResult:
+    """Alg. 1 on physical states x_phys [n][C][L][L] with nlp_phys = -log P(x_phys) + const.
+    `nlp_fn(x)` evaluates the same for replay-buffer states; `init` optionally
+    continues from filters (W, hbias, vbias) instead of the Alg. 1 initialisation."""
     dev = x_phys.device
+    C = int(x_phys.shape[1])
     L = int(x_phys.shape[-1])
-    beta = 1.0 / T
-    f0 = workloads.alg1_init_filters(K, Lw, seed=seed)
-    W = torch.tensor(f0.W, device=dev, requires_grad=True)
-    hb = torch.tensor(f0.hbias, device=dev, requires_grad=True)
-    vb = torch.tensor(f0.vbias, device=dev, requires_grad=True)
+    if init is None:
+        f0 = workloads.alg1_init_filters(K, Lw, seed=seed, C=C)
+        W, hb, vb = _params_of(f0, dev)
+    else:
+        W, hb, vb = (t.detach().clone().to(dev).requires_grad_(True) for t in init)
     opt = torch.optim.Adam([W, hb, vb], lr=lr)
     N = train_size or int(x_phys.shape[0])
     gen = torch.Generator(device="cpu").manual_seed(seed)
-    # buffer starts from Binomial(p = 0.5) states (Alg. 1)
-    buf = torch.from_numpy(workloads.random_states(ub, 1, L, seed=seed + 1)).to(dev)
-    xb = buf.clone()
-    Eb = api.ising_energy(xb)
+    nlp_phys = nlp_phys.to(device=dev, dtype=torch.float64)
+    if replay:
+        # buffer starts from Binomial(p = 0.5) states (Alg. 1)
+        buf = torch.from_numpy(workloads.random_states(ub, C, L, seed=seed + 1)).to(dev)
+        xb = buf.clone()
+        nb = nlp_fn(xb)
     losses = []
     steps = 0
-    t_sweep = 0
     for ep in range(epochs):
-        # UPDATE BUFFER: k Gibbs steps of the current CRBM from the previous new states
-        p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev)
-        job = api.Job(p, api.GIBBS, L, np.full(ub, T), seed=seed + 1000 + ep, gibbs_k=gibbs_k, state=buf)
-        job.run(1)
-        buf = job.state.clone()
-        t_sweep += 1
-        xb = torch.cat([buf, xb])[:N]
-        Eb = torch.cat([api.ising_energy(buf), Eb])[:N]
-        x_tot = torch.cat([x_phys, xb])
-        E_tot = torch.cat([E_phys, Eb]).to(torch.float64)
+        if replay:
+            # UPDATE BUFFER: k Gibbs steps of the current CRBM from the previous new states
+            p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev)
+            job = api.Job(p, api.GIBBS, L, np.full(ub, T), seed=seed + 1000 + ep, gibbs_k=gibbs_k, state=buf)
+            job.run(1)
+            buf = job.state.clone()
+            job.close()
+            xb = torch.cat([buf, xb])[:N]
+            nb = torch.cat([nlp_fn(buf), nb])[:N]
+            x_tot = torch.cat([x_phys, xb])
+            n_tot = torch.cat([nlp_phys, nb.to(torch.float64)])
+        else:
+            x_tot, n_tot = x_phys, nlp_phys
         perm = torch.randperm(x_tot.shape[0], generator=gen).to(dev)
         for s0 in range(0, x_tot.shape[0] - batch + 1, batch):
             idx = perm[s0:s0 + batch]
             F = api.crbm_free_energy_fn(x_tot[idx], W, hb, vb)
-            diff = beta * E_tot[idx] - F
-            C = diff.mean()
-            loss = ((diff - C) ** 2).mean()
+            diff = n_tot[idx] - F
+            Cc = diff.mean()
+            loss = ((diff - Cc) ** 2).mean()
             opt.zero_grad(set_to_none=True)
             loss.backward()
             opt.step()
@@ -95,9 +124,47 @@ def train(x_phys: torch.Tensor, E_phys: torch.Tensor, T: float, K: int = 8, Lw: 
     return TrainResult(W.detach().clone(), hb.detach().clone(), vb.detach().clone(), losses, steps)
 
 
+def train(x_phys: torch.Tensor, E_phys: torch.Tensor, T: float, **kw) -> TrainResult:
+    """Alg. 1 for the Ising model: physical states with their energies E (J = 1)."""
+    return train_crbm(x_phys, E_phys.to(torch.float64) / T, ising_nlp(T), T, **kw)
+
+
 def full_loss(x: torch.Tensor, E: torch.Tensor, T: float, W, hb, vb) -> float:
+    """The Ising loss of Eq. (loss) with its optimal constant over the whole set."""
+    return full_loss_nlp(x, E.to(torch.float64) / T, W, hb, vb)
+
+
+def full_loss_nlp(x: torch.Tensor, nlp: torch.Tensor, W, hb, vb) -> float:
     """The loss of Eq. (loss) with its optimal constant over the whole set."""
     p = api.CRBMParams(W, hb, vb, device=W.device)
     F = api.free_energy(p, x)
-    diff = E.to(torch.float64) / T - F
+    diff = nlp.to(torch.float64) - F
     return float(((diff - diff.mean()) ** 2).mean())
+
+
+def kitaev_pretrain_and_train(L: int, T: float, K: int = 8, Lw: int = 3, n_random: int = 4096, n_phys: int = 512,
+                              pre_epochs: int = 10, epochs: int = 10, sweeps: int = 200, lr: float = 1e-3,
+                              seed: int = 0, J=(1.0, 1.0, 1.0)):
+    """Sec. IV pre-training of a Kitaev CRBM (C = 3 bond channels): Alg. 1's loss
+    on uniformly random gauge configurations, then physical samples drawn with
+    the pre-trained CRBM (persistent replicas, exchange-corrected) and Alg. 1
+    with the replay buffer on them.  Returns (pretrained, trained, physical
+    samples, their exchange acceptance, the random pre-training states)."""
+    dev = torch.device("cuda")
+    nlp = kitaev_nlp(T, J)
+    xr = torch.from_numpy(workloads.random_states(n_random, 3, L, seed=seed + 7)).to(dev)
+    pre = train_crbm(xr, nlp(xr), nlp, T, K=K, Lw=Lw, epochs=pre_epochs, batch=64, lr=lr, seed=seed, replay=False)
+    p = api.CRBMParams(pre.W, pre.hbias, pre.vbias, device=dev)
+    job = api.Job(p, api.KITAEV, L, np.full(n_phys, T), seed=seed + 11, J=J, replica=True)
+    done = 0
+    while done < sweeps:
+        b = min(50, sweeps - done)
+        job.run(b)
+        done += b
+    x = job.state.clone()
+    st = job.stats()
+    acc = float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
+    job.close()
+    fin = train_crbm(x, nlp(x), nlp, T, K=K, Lw=Lw, epochs=epochs, batch=20, lr=lr, ub=128, seed=seed + 1,
+                     init=(pre.W, pre.hbias, pre.vbias))
+    return pre, fin, x, acc, xr

@@ -68,6 +68,7 @@ def test_workspace_size_validation(lib):
     assert _lib.crbm_workspace_size(_params(), _desc(L=257)) == 0
     assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=13)) == 0
     assert _lib.crbm_workspace_size(_params(), _desc(target=2, rbm=0x1000)) == 0  # replica needs a target
+    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=2)) > 0            # Gibbs-only chains, C = 3
     assert _lib.crbm_workspace_size(_params(), _desc(rbm=0x1000)) > 0
     # Kitaev keeps the singular values of every chain: 4 chains x 36 doubles more
     kit = _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=6))

@@ -64,3 +64,28 @@ def test_training_reduces_loss_and_transfers(mods):
         st = job.stats()
         return st["n_acc"].sum() / st["sweeps"].sum()
     assert acceptance(r.W, r.hbias, r.vbias) >= acceptance(W0, z, torch.zeros(1, device="cuda"))
+
+
+def test_kitaev_pretraining_and_self_samples(mods):
+    # Sec. IV: pre-training on random gauge configurations (C = 3 bond channels),
+    # then training on samples the pre-trained CRBM itself drew through the
+    # exchange-corrected sampler (ADAM at the paper's 1e-3)
+    api, train = mods
+    L, T = 4, 0.3
+    pre, fin, x, acc, xr = train.kitaev_pretrain_and_train(L, T, n_random=1024, n_phys=256, pre_epochs=6,
+                                                           epochs=6, sweeps=60, seed=0)
+    assert 0.05 < acc <= 1.0
+    nlp = train.kitaev_nlp(T)
+    f0 = WL.alg1_init_filters(8, 3, seed=0, C=3)
+    W0 = torch.tensor(f0.W, device="cuda")
+    z8, z3 = torch.zeros(8, device="cuda"), torch.zeros(3, device="cuda")
+    nr = nlp(xr)
+    l0_r = train.full_loss_nlp(xr, nr, W0, z8, z3)
+    lp_r = train.full_loss_nlp(xr, nr, pre.W, pre.hbias, pre.vbias)
+    assert lp_r < 0.9 * l0_r, (l0_r, lp_r)
+    nx = nlp(x)
+    lp_x = train.full_loss_nlp(x, nx, pre.W, pre.hbias, pre.vbias)
+    lf_x = train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)
+    assert np.isfinite(lf_x) and lf_x < 1.1 * lp_x, (lp_x, lf_x)
+    # the replay buffer ran three-channel Gibbs-only chains
+    assert fin.W.shape == (8, 3, 3, 3)
