@@ -251,19 +251,33 @@ __device__ __forceinline__ double preact_v_exact(const float* __restrict__ W, fl
     return acc;
 }
 
-// FP64 free energy of a bit plane, over the workgroup
+// FP64 free energy of a bit plane, over the workgroup.  Wl and hbl are LDS
+// copies of the filters and hidden biases; channel-major so that a channel's
+// taps are read by every lane at the same address.
 template <int LW>
-__device__ double free_energy_exact(const float* __restrict__ W, const float* hbs, float vb, const uint32_t* pl,
-                                    int RS, int L, int K, double* red, const double* dc)
+__device__ double free_energy_exact(const float* Wl, const float* hbl, float vb, const uint32_t* pl, int RS, int L,
+                                    int K, double* red, const double* dc)
 {
-    const int LL = L * L;
+    const int LL = L * L, lgL = 31 - __builtin_clz(L), Lm = L - 1;
     double f = 0.0;
-    for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
-        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        f -= softplus_c(preact_h_exact<LW>(W, hbs[k], pl, RS, L, k, i, j), dc);
+    for (int k = 0; k < K; ++k) {
+        const float* Wk = Wl + k * LW * LW;
+        const double hb = (double)hbl[k];
+        for (int q = threadIdx.x; q < LL; q += blockDim.x) {
+            const int i = q >> lgL, j = q & Lm;
+            double acc = hb;
+#pragma unroll
+            for (int a = 0; a < LW; ++a) {
+                const uint32_t w = window32(pl + ((i + a) & Lm) * RS, j);
+#pragma unroll
+                for (int b2 = 0; b2 < LW; ++b2)
+                    if ((w >> b2) & 1u) acc += (double)Wk[a * LW + b2];
+            }
+            f -= softplus_c(acc, dc);
+        }
     }
     for (int q = threadIdx.x; q < LL; q += blockDim.x) {
-        const int i = q / L, j = q - i * L;
+        const int i = q >> lgL, j = q & Lm;
         if (bit_at(pl + i * RS, j)) f -= (double)vb;
     }
     return block_sum(f, red);
@@ -427,7 +441,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     float* dApre = Sk + K;     // bound on |a_f32 - a| (additive mode)
     float* ehbm = dApre + K;   // e^{-h_b}
     float* ehbp = ehbm + K;    // e^{+h_b}
-    double* red = (double*)(smem + (((size_t)(3 * tsz + 6 * K) * 4 + 15) & ~(size_t)15));
+    float* hbl = ehbp + K;     // h_b
+    float* Wl = hbl + K;       // the filters, for the exact paths
+    double* red = (double*)(smem + (((size_t)(3 * tsz + 7 * K + K * LW * LW) * 4 + 15) & ~(size_t)15));
     uint32_t* vpl = (uint32_t*)(red + 64);
     uint32_t* hpl = vpl + 3 * PL;
     __shared__ float sh_vb, sh_dAv, sh_vb_raw, sh_evbm, sh_Sv;
@@ -448,8 +464,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
 
     const float* __restrict__ W = J.W;
     constexpr float NLOG2E = -1.44269504088896341f;
+    for (int q = tid; q < K * LW * LW; q += NT) Wl[q] = W[q];
     for (int k = tid; k < K; k += NT) {
         const float hb = J.hb[k];
+        hbl[k] = hb;
         float s = fabsf(hb);
         for (int q = 0; q < LW * LW; ++q) s += fabsf(W[k * LW * LW + q]);
         Sk[k] = s;
@@ -677,7 +695,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                             const int k = (int)(q >> (2 * lgL)), i = (int)(q >> lgL) & Lm, j = (int)q & Lm;
                             const u32x4 rn = philox10_uk(q >> 2, t, gid, tagh, k0, k1);
                             const bool on =
-                                bernoulli_exact_c(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
+                                bernoulli_exact_c(preact_h_exact<LW>(Wl, hbl[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
                             put_bit(hpl + k * PL, RS, L, i, j, on);
                         }
                     } else {
@@ -685,7 +703,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                             const int k = q >> (2 * lgL), i = (q >> lgL) & Lm, j = q & Lm;
                             const u32x4 rn = philox10_uk((uint32_t)q >> 2, t, gid, tagh, k0, k1);
                             const bool on =
-                                bernoulli_exact_c(preact_h_exact<LW>(W, J.hb[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
+                                bernoulli_exact_c(preact_h_exact<LW>(Wl, hbl[k], vs, RS, L, k, i, j), word_of(rn, j & 3), sh_dc);
                             put_bit(hpl + k * PL, RS, L, i, j, on);
                         }
                     }
@@ -772,7 +790,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                             const int x = (int)(q >> lgL), y = (int)q & Lm;
                             const u32x4 rn = philox10_uk(q >> 2, t, gid, tagv, k0, k1);
                             const bool on =
-                                bernoulli_exact_c(preact_v_exact<LW>(W, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
+                                bernoulli_exact_c(preact_v_exact<LW>(Wl, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
                             put_bit(vd, RS, L, x, y, on);
                         }
                     } else {
@@ -780,7 +798,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                             const int x = q >> lgL, y = q & Lm;
                             const u32x4 rn = philox10_uk((uint32_t)q >> 2, t, gid, tagv, k0, k1);
                             const bool on =
-                                bernoulli_exact_c(preact_v_exact<LW>(W, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
+                                bernoulli_exact_c(preact_v_exact<LW>(Wl, sh_vb_raw, hpl, PL, RS, L, K, x, y), word_of(rn, y & 3), sh_dc);
                             put_bit(vd, RS, L, x, y, on);
                         }
                     }
@@ -884,8 +902,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         double Fnew = Fp, Bnew = Bp, Fold = 0.0;
         if (flag == 2) {
             // inside the float32 band: decide with FP64 free energies of both states
-            Fnew = free_energy_exact<LW>(W, J.hb, sh_vb_raw, vp, RS, L, K, red, sh_dc);
-            Fold = free_energy_exact<LW>(W, J.hb, sh_vb_raw, vpl + cur * PL, RS, L, K, red, sh_dc);
+            Fnew = free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vp, RS, L, K, red, sh_dc);
+            // the cached F of the current state is already exact after an earlier re-check
+            Fold = sh_Bcur > 0.0 ? free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vpl + cur * PL, RS, L, K, red, sh_dc)
+                                 : R.F;
             Bnew = 0.0;
             if (tid == 0) {
                 const double logr = -(1.0 / J.T[g]) * J.J0 * (double)(Ep - R.E) + (Fnew - Fold);
@@ -958,7 +978,7 @@ int ising_fast_threads(int L)
 size_t ising_fast_lds_bytes(int K, int LW, int L)
 {
     const size_t tsz = (size_t)K * LW * ((size_t)1 << LW);
-    size_t o = ((3 * tsz + 6 * (size_t)K) * 4 + 15) & ~(size_t)15;
+    size_t o = ((3 * tsz + 7 * (size_t)K + (size_t)K * LW * LW) * 4 + 15) & ~(size_t)15;
     o += 64 * 8;
     const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
     o += (3 + (size_t)K) * (size_t)L * RS * 4;
