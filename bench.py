@@ -40,9 +40,9 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 # after any change to them `traffic` is reported as null until re-measured.
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
                   "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": "b52d9cf74ac9adec88ed708341947698e7489b8995da942bd95777eb8e518847",
+MEASURED_TRAFFIC = {"sources_sha256": "f537ca5418cd28debb81b32de26f2d6b83ab483672a43d565c7ce913413e9ff3",
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
-                    "fetch_kib": 9312.9, "fetch_scale": 2.0, "write_kib": 20115.0, "write_scale": 1.0}
+                    "fetch_kib": 9312.9, "fetch_scale": 2.0, "write_kib": 20114.7, "write_scale": 1.0}
 
 
 def kernel_sources_sha256():
@@ -209,6 +209,46 @@ def tempering(blocks=20, block_sweeps=5):
             "exchange_acceptance": float(st["n_acc"].sum() / st["sweeps"].sum()),
             "swap_acceptance": float(st["n_swap"].sum() / 2 / max(1, pairs + ((rungs // 2) * nl))),
             "swap_round_ms": swap_ms}
+    return out
+
+
+def autocorrelation_times(sizes=(16, 32, 64, 128), chains=64, burn=1000, record=8000, max_lag=2000):
+    """Integrated autocorrelation time of the energy (automatic window, c = 6)
+    for the CRBM sampler with the exact Ising kernels of App. C (K=2, 2x2) at
+    T = 2.2 and T = T_c, the temperatures of the Sec. III comparison: per L,
+    `chains` independent chains, `burn` sweeps, then `record` sweeps kept in
+    the device trace ring; mean and standard error of tau over the chains,
+    and the time of one autocorrelation launch over all of them."""
+    import math
+
+    from paper_2008_05401_amd import api, workloads as WL
+    out = {}
+    tc = 2.0 / math.log(1.0 + math.sqrt(2.0))
+    for tname, T in (("T2.2", 2.2), ("Tc", tc)):
+        f = WL.analytic_ising_filters(T)
+        for L in sizes:
+            job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, np.full(chains, T), seed=L)
+            for _ in range(burn // 100):
+                job.run(100)
+            job.record_trace(record)
+            for _ in range(record // 100):
+                job.run(100)
+            ring, start, count = job.trace_ring()
+            res = {}
+
+            def go():
+                res["r"] = api.autocorrelation(ring, max_lag, start=start)
+            ms = _timed(go)
+            _, tau, win = (t.cpu().numpy() for t in res["r"])
+            st = job.stats()
+            ok = win > 0
+            out[f"{tname}_L{L}"] = {
+                "tau_int_mean": float(tau[ok].mean()) if ok.any() else None,
+                "tau_int_sem": float(tau[ok].std(ddof=1) / np.sqrt(ok.sum())) if ok.sum() > 1 else None,
+                "chains_with_window": int(ok.sum()), "chains": chains, "recorded_sweeps": count,
+                "acceptance": float(st["n_acc"].sum() / st["sweeps"].sum()),
+                "autocorr_kernel_ms": ms}
+            job.close()
     return out
 
 
@@ -405,6 +445,7 @@ def main():
                   "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds_tbs / PEAK_LDS_TBS}
     if not args.no_extra:
         out["kitaev"] = kitaev()
+        out["autocorrelation"] = autocorrelation_times()
         out["tempering"] = tempering()
         out["training"] = training_and_transfer()
         out["kitaev_training"] = kitaev_training_and_transfer()

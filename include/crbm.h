@@ -176,6 +176,28 @@ CRBM_API crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_c
  * use each round index once.  Not allowed with CRBM_GIBBS. */
 CRBM_API crbm_status crbm_tempering_swap(crbm_ctx* ctx, int32_t n_ladders, int32_t round);
 
+/* Per-sweep observable trace, the input of integrated autocorrelation times
+ * (the sampler diagnostic of Sec. III and IV): with trace != NULL, sweep t of
+ * chain g stores the energy of the chain's state after the sweep (Ising: E/J;
+ * Kitaev: the fermion energy E_f) at trace[g * trace_len + t % trace_len]
+ * (device, FP64, caller-owned, [n_chains][trace_len]).  NULL or trace_len = 0
+ * switches it off.  Stream-ordered like the sweeps. */
+CRBM_API crbm_status crbm_set_trace(crbm_ctx* ctx, double* trace, int32_t trace_len);
+
+/* Autocovariance and integrated autocorrelation time of n series
+ * x_{g,i} = trace[g * len + (start + i) % len], i = 0..len-1 (device FP64),
+ * the diagnostic by which Sec. III and IV compare samplers:
+ *   out[g][t] = C(t) = 1/(len - t) sum_{i < len - t} (x_i - m)(x_{i+t} - m),
+ *   m the series mean, t = 0..max_lag (device, [n][max_lag + 1]);
+ *   tau[g] = 1/2 + sum_{t=1..W} C(t)/C(0) with W the smallest lag >= 1 such
+ *   that W >= c_window * tau(W) (automatic windowing), window[g] = W, or -1
+ *   with tau summed to max_lag when no lag qualifies or C(0) = 0.
+ * tau and window (device, [n]) may both be NULL for the autocovariance alone.
+ * 1 <= len <= 8176 (the series is held in 64 KiB of LDS), 0 <= max_lag < len,
+ * c_window > 0.  Async on `stream`. */
+CRBM_API crbm_status crbm_autocorr(const double* trace, int32_t n, int32_t len, int32_t start, int32_t max_lag,
+                                   double c_window, double* out, double* tau, int32_t* window, void* stream);
+
 /* Copy the per-chain records, n_chains x crbm_chain_stats, to `out`
  * (device memory if on_device != 0, else host memory; the host copy
  * synchronises the stream). */

@@ -86,7 +86,7 @@ def lib():
                                      ct.c_uint32, ct.c_uint32, vp]
         L.orc_gibbs_step.restype = ct.c_int64
         L.orc_chain_init.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp, vp]
-        L.orc_run.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp, vp, ct.c_uint32, ct.c_int, vp, vp, vp]
+        L.orc_run.argtypes = [P(_Params), P(_RunDesc), vp, vp, vp, vp, ct.c_uint32, ct.c_int, vp, vp, vp, vp]
         L.orc_tempering_swap.argtypes = [P(_RunDesc), ct.c_int, vp, vp, vp, vp, ct.c_int, ct.c_uint32, vp]
         L.orc_pt_uniform.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_uint32]
         L.orc_pt_uniform.restype = ct.c_double
@@ -278,14 +278,20 @@ class Chains:
         lib().orc_chain_init(m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state), _ptr(self.rec),
                              _ptr(self.eps) if self.eps is not None else None)
 
-    def run(self, n_sweeps: int, log_accepts: bool = False):
+    def run(self, n_sweeps: int, log_accepts: bool = False, log_energy: bool = False):
+        """Advance every chain n_sweeps.  Returns the accept log [n, n_sweeps]
+        (or None); with log_energy the energy after each sweep (Ising E/J,
+        Kitaev E_f) is left in self.energy_log [n, n_sweeps]."""
         n = self.T.shape[0]
         acc = np.zeros((n, n_sweeps), np.uint8) if log_accepts else None
+        elog = np.zeros((n, n_sweeps), np.float64) if log_energy else None
         lib().orc_run(self.m.p, ct.byref(self.desc), _ptr(self.T), _ptr(self.state),
                       _ptr(self.rbm) if self.rbm is not None else None,
                       _ptr(self.eps) if self.eps is not None else None, self.t, n_sweeps,
-                      _ptr(self.rec), _ptr(self.ties), _ptr(acc) if acc is not None else None)
+                      _ptr(self.rec), _ptr(self.ties), _ptr(acc) if acc is not None else None,
+                      _ptr(elog) if elog is not None else None)
         self.t += n_sweeps
+        self.energy_log = elog
         return acc
 
     def tempering_swap(self, n_ladders: int, round_: int):

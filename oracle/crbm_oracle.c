@@ -435,9 +435,12 @@ ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const do
  * With a replica: accepted -> state <- x', replica <- old state; rejected ->
  * replica <- x'.  For Kitaev, `eps` (if not NULL) keeps the singular values
  * of every chain's current state, [n_chains][L*L].
- * ties[0] counts Gibbs near-ties, ties[1] counts |log r - log u| < 1e-6.  */
+ * ties[0] counts Gibbs near-ties, ties[1] counts |log r - log u| < 1e-6.
+ * accept_log / energy_log (optional, [n_chains][n_sweeps]) record each sweep's
+ * decision and the energy after it (Ising E/J, Kitaev E_f).  */
 ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T, int8_t* state, int8_t* rbm,
-                     double* eps, uint32_t t0, int n_sweeps, orc_chain* rec, int64_t* ties, uint8_t* accept_log)
+                     double* eps, uint32_t t0, int n_sweeps, orc_chain* rec, int64_t* ties, uint8_t* accept_log,
+                     double* energy_log)
 {
     const int C = P->C, L = D->L, n = L * L, nv = C * n;
     int64_t gt = 0, mt = 0;
@@ -496,6 +499,8 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                     memcpy(y, sp, (size_t)nv); /* the replica keeps its Gibbs steps */
                 }
                 R->sweeps += 1;
+                if (energy_log)
+                    energy_log[(size_t)g * n_sweeps + it] = D->target != 1 ? (double)R->E : R->Ef;
                 if ((int64_t)t >= (int64_t)D->burnin) {
                     R->n_meas += 1;
                     if (D->target != 1) {

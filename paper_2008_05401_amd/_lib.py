@@ -44,7 +44,7 @@ STATS_DTYPE = np.dtype([
 assert STATS_DTYPE.itemsize == 160
 
 EXPORTS = ["crbm_workspace_size", "crbm_init", "crbm_propose_accept", "crbm_propose_accept_many",
-           "crbm_tempering_swap",
+           "crbm_tempering_swap", "crbm_set_trace", "crbm_autocorr",
            "crbm_read_stats", "crbm_sweeps_done", "crbm_destroy", "crbm_free_energy", "target_energy",
            "crbm_grad_workspace_size", "crbm_grad", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
            "crbm_version"]
@@ -67,6 +67,8 @@ def load(path: str = LIB_PATH):
     L.crbm_propose_accept.argtypes = [vp, ct.c_int32]
     L.crbm_propose_accept_many.argtypes = [P(vp), ct.c_int32, ct.c_int32]
     L.crbm_tempering_swap.argtypes = [vp, ct.c_int32, ct.c_int32]
+    L.crbm_set_trace.argtypes = [vp, vp, ct.c_int32]
+    L.crbm_autocorr.argtypes = [vp, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, vp, vp, vp, vp]
     L.crbm_read_stats.argtypes = [vp, vp, ct.c_int32]
     L.crbm_sweeps_done.argtypes = [vp]
     L.crbm_sweeps_done.restype = ct.c_int64
@@ -83,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.crbm_last_error.restype = ct.c_char_p
     L.crbm_version.restype = ct.c_char_p
     for name in ("crbm_init", "crbm_propose_accept", "crbm_propose_accept_many", "crbm_tempering_swap",
+                 "crbm_set_trace", "crbm_autocorr",
                  "crbm_read_stats",
                  "crbm_destroy", "crbm_free_energy", "target_energy", "crbm_grad"):
         getattr(L, name).restype = ct.c_int
@@ -117,6 +120,16 @@ def crbm_propose_accept_many(ctxs, n_sweeps: int):
 
 def crbm_tempering_swap(ctx, n_ladders: int, round_: int):
     check(load().crbm_tempering_swap(ctx, int(n_ladders), int(round_)))
+
+
+def crbm_set_trace(ctx, trace_ptr, trace_len: int):
+    check(load().crbm_set_trace(ctx, trace_ptr, int(trace_len)))
+
+
+def crbm_autocorr(trace_ptr, n: int, length: int, start: int, max_lag: int, c_window: float, out_ptr, tau_ptr,
+                  window_ptr, stream):
+    check(load().crbm_autocorr(trace_ptr, int(n), int(length), int(start), int(max_lag), float(c_window), out_ptr,
+                               tau_ptr, window_ptr, stream))
 
 
 def crbm_read_stats(ctx, out_ptr: int, on_device: bool):

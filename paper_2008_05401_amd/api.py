@@ -123,6 +123,33 @@ class Job:
         C.crbm_tempering_swap(self.ctx, int(n_ladders), int(round_))
         return self
 
+    def record_trace(self, length: int):
+        """Keep the energy after each sweep (Ising E/J, Kitaev E_f) of every chain
+        in a device ring buffer of `length` sweeps; 0 switches recording off."""
+        length = int(length)
+        if length <= 0:
+            C.crbm_set_trace(self.ctx, None, 0)
+            self._trace = None
+            return self
+        self._trace = torch.zeros((self.n_chains, length), dtype=torch.float64, device=self.state.device)
+        self._trace_from = self.sweeps
+        C.crbm_set_trace(self.ctx, self._trace.data_ptr(), length)
+        return self
+
+    def trace_ring(self):
+        """(ring buffer [n_chains, length], start, count): the recorded energies
+        in time order are ring[:, (start + i) % length] for i < count."""
+        length = int(self._trace.shape[1])
+        done = self.sweeps
+        count = min(done - self._trace_from, length)
+        return self._trace, (done - count) % length, count
+
+    def trace(self) -> torch.Tensor:
+        """Recorded energies in time order, [n_chains, count]."""
+        ring, start, count = self.trace_ring()
+        idx = (torch.arange(count, device=ring.device) + start) % ring.shape[1]
+        return ring[:, idx]
+
     @property
     def sweeps(self) -> int:
         return C.crbm_sweeps_done(self.ctx)
@@ -152,6 +179,21 @@ class Job:
 def run_many(jobs, n_sweeps: int):
     """Advance several jobs (same stream) by n_sweeps in shared launches."""
     C.crbm_propose_accept_many([j.ctx for j in jobs], int(n_sweeps))
+
+
+def autocorrelation(series: torch.Tensor, max_lag: int, c_window: float = 6.0, start: int = 0, stream=None):
+    """Autocovariance C(t), t = 0..max_lag, integrated autocorrelation time and
+    its automatic window for every row of `series` ([n, len] FP64 on the GPU;
+    row g read as series[g, (start + i) % len]).  Returns (C [n, max_lag+1],
+    tau [n], window [n]; window -1 where no lag up to max_lag qualifies)."""
+    s = series.to(dtype=torch.float64).contiguous()
+    n, ln = int(s.shape[0]), int(s.shape[1])
+    out = torch.empty((n, int(max_lag) + 1), dtype=torch.float64, device=s.device)
+    tau = torch.empty(n, dtype=torch.float64, device=s.device)
+    win = torch.empty(n, dtype=torch.int32, device=s.device)
+    C.crbm_autocorr(s.data_ptr(), n, ln, int(start), int(max_lag), float(c_window), out.data_ptr(), tau.data_ptr(),
+                    win.data_ptr(), _stream_ptr(stream))
+    return out, tau, win
 
 
 def free_energy(params: CRBMParams, x: torch.Tensor, stream=None) -> torch.Tensor:

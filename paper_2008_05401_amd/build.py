@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrbm.so")
-SOURCES = ["crbm_abi.cpp", "init.hip", "sweep_generic.hip", "sweep_ising.hip", "ops.hip", "tempering.hip"]
+SOURCES = ["crbm_abi.cpp", "init.hip", "sweep_generic.hip", "sweep_ising.hip", "ops.hip", "tempering.hip", "autocorr.hip"]
 ARCH = os.environ.get("CRBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

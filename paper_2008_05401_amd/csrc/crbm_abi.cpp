@@ -320,6 +320,32 @@ crbm_status crbm_tempering_swap(crbm_ctx* ctx, int32_t n_ladders, int32_t round)
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "tempering swap launch");
 }
 
+crbm_status crbm_set_trace(crbm_ctx* ctx, double* trace, int32_t trace_len)
+{
+    if (!ctx) return fail(CRBM_EINVAL, "ctx is NULL");
+    if (trace_len < 0) return fail(CRBM_EINVAL, "trace_len=%d must be >= 0", trace_len);
+    ctx->job.trace = (trace && trace_len > 0) ? trace : nullptr;
+    ctx->job.trace_len = (trace && trace_len > 0) ? trace_len : 0;
+    hipError_t e = hipMemcpyAsync(ctx->job_dev, &ctx->job, sizeof(JobDev), hipMemcpyHostToDevice, ctx->stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "hipMemcpyAsync(job)");
+}
+
+crbm_status crbm_autocorr(const double* trace, int32_t n, int32_t len, int32_t start, int32_t max_lag,
+                          double c_window, double* out, double* tau, int32_t* window, void* stream)
+{
+    if (n < 0) return fail(CRBM_EINVAL, "n=%d must be >= 0", n);
+    if (len < 1 || len > 8176) return fail(CRBM_EINVAL, "len=%d outside [1,8176]", len);
+    if (max_lag < 0 || max_lag >= len) return fail(CRBM_EINVAL, "max_lag=%d outside [0,len)", max_lag);
+    if (start < 0) return fail(CRBM_EINVAL, "start=%d must be >= 0", start);
+    if (!(c_window > 0.0)) return fail(CRBM_EINVAL, "c_window must be > 0");
+    if ((tau == nullptr) != (window == nullptr)) return fail(CRBM_EINVAL, "tau and window are both set or both NULL");
+    if (n == 0) return CRBM_OK;
+    if (!trace || !out) return fail(CRBM_EINVAL, "trace and out must be device pointers");
+    hipError_t e = launch_autocorr(trace, n, len, start % len, max_lag, c_window, out, tau, window,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_autocorr launch");
+}
+
 crbm_status crbm_read_stats(crbm_ctx* ctx, crbm_chain_stats* out, int32_t on_device)
 {
     if (!ctx || !out) return fail(CRBM_EINVAL, "ctx and out must not be NULL");

@@ -18,11 +18,13 @@ struct JobDev {
     int8_t* rbm_state;  // persistent CRBM replicas or nullptr
     ChainRec* rec;
     double* eps;        // Kitaev: singular values of every chain's current state [n_chains][L*L]
+    double* trace;      // per-sweep energy ring buffer [n_chains][trace_len] or nullptr
     double J0, J1, J2;
     uint64_t seed;
     int K, C, LW, target, L, n_chains, gibbs_k, burnin;
     uint32_t chain_offset;
     int init_state;
+    int trace_len;
 };
 
 constexpr int MAX_JOBS_PER_LAUNCH = 128;
@@ -40,6 +42,8 @@ struct SweepLaunch {
 };
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target);
+hipError_t launch_autocorr(const double* trace, int n, int len, int start, int max_lag, double c_win, double* out,
+                           double* tau, int* window, hipStream_t s);
 hipError_t launch_tempering_swap(const JobDev* job_dev, int n_pairs, int n_ladders, int q0, uint32_t round,
                                  int target, hipStream_t s);
 size_t init_lds(int K, int C, int LW, int L, int target);

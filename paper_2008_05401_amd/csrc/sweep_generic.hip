@@ -216,6 +216,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
                 sh_M = Mcur;
             }
             R.sweeps += 1;
+            if (J.trace) J.trace[(size_t)g * J.trace_len + t % (uint32_t)J.trace_len] = ising ? (double)R.E : R.Ef;
             if ((long long)t >= (long long)J.burnin) {
                 R.n_meas += 1;
                 if (ising) {

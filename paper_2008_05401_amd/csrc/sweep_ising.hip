@@ -925,6 +925,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
                 R.n_acc += 1;
             }
             R.sweeps += 1;
+            if (J.trace) J.trace[(size_t)g * J.trace_len + t % (uint32_t)J.trace_len] = (double)R.E;
             if ((long long)t >= (long long)J.burnin) {
                 const long long mm = flag ? Mp : sh_Mcur;
                 R.n_meas += 1;

@@ -123,3 +123,16 @@ def served_job_stream(n_jobs: int, rate_per_s: float = 200.0, n_sweeps: int = 20
 def random_states(n: int, C: int, L: int, seed: int = 0, p_up: float = 0.5) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.where(rng.random((n, C, L, L)) < p_up, 1, -1).astype(np.int8)
+
+
+def ar1_series(n: int, length: int, phi: float, seed: int = 0) -> np.ndarray:
+    """n stationary AR(1) series x_{i+1} = phi x_i + e_i, e ~ N(0, 1), started
+    from the stationary law N(0, 1/(1-phi^2)); [n, length] float64.  Its
+    integrated autocorrelation time is (1+phi) / (2 (1-phi))."""
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal((n, length))
+    x = np.empty((n, length))
+    x[:, 0] = e[:, 0] / math.sqrt(1.0 - phi * phi)
+    for i in range(1, length):
+        x[:, i] = phi * x[:, i - 1] + e[:, i]
+    return x

@@ -104,6 +104,16 @@ def test_other_entry_points_validate(lib):
     assert L.crbm_propose_accept(None, 1) == _lib.CRBM_EINVAL
     assert L.crbm_propose_accept_many(None, 1, 1) == _lib.CRBM_EINVAL
     assert L.crbm_tempering_swap(None, 1, 0) == _lib.CRBM_EINVAL
+    assert L.crbm_set_trace(None, 0x1000, 4) == _lib.CRBM_EINVAL
+    ac = L.crbm_autocorr
+    assert ac(0x1000, 1, 8177, 0, 3, 6.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL   # longest series 8176
+    assert ac(0x1000, 1, 0, 0, 0, 6.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL      # empty series
+    assert ac(0x1000, 1, 8, 0, 8, 6.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL      # max_lag >= len
+    assert ac(0x1000, 1, 8, -1, 3, 6.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL     # negative start
+    assert ac(0x1000, 1, 8, 0, 3, 0.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL      # window constant
+    assert ac(0x1000, 1, 8, 0, 3, 6.0, 0x1000, 0x1000, None, None) == _lib.CRBM_EINVAL    # tau without window
+    assert ac(None, 1, 8, 0, 3, 6.0, 0x1000, None, None, None) == _lib.CRBM_EINVAL
+    assert ac(None, 0, 8, 0, 3, 6.0, None, None, None, None) == _lib.CRBM_OK              # no series
 
 
 def test_stats_record_layout(lib):
