@@ -36,13 +36,14 @@ def build(force: bool = True) -> str:
 
 class _Params(ct.Structure):
     _fields_ = [("K", ct.c_int32), ("C", ct.c_int32), ("Lw", ct.c_int32),
-                ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p)]
+                ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p),
+                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32)]
 
 
 class _RunDesc(ct.Structure):
     _fields_ = [("target", ct.c_int32), ("L", ct.c_int32), ("n_chains", ct.c_int32),
                 ("gibbs_k", ct.c_int32), ("burnin", ct.c_int32), ("g0", ct.c_uint32),
-                ("seed", ct.c_uint64), ("J", ct.c_double * 3)]
+                ("seed", ct.c_uint64), ("J", ct.c_double * 3), ("boundary", ct.c_int32)]
 
 
 CHAIN_DTYPE = np.dtype([
@@ -71,16 +72,16 @@ def lib():
         L.orc_hidden_preact.argtypes = [P(_Params), vp, ct.c_int, vp]
         L.orc_visible_preact.argtypes = [P(_Params), vp, ct.c_int, vp]
         L.orc_free_energy.argtypes = [P(_Params), vp, ct.c_int, ct.c_int, vp]
-        L.orc_ising_energy.argtypes = [vp, ct.c_int]
+        L.orc_ising_energy.argtypes = [vp, ct.c_int, ct.c_int]
         L.orc_ising_energy.restype = ct.c_int64
         L.orc_magnetization.argtypes = [vp, ct.c_int]
         L.orc_magnetization.restype = ct.c_int64
-        L.orc_kitaev_matrix.argtypes = [vp, ct.c_int, ct.c_int, vp, vp]
+        L.orc_kitaev_matrix.argtypes = [vp, ct.c_int, ct.c_int, vp, ct.c_int, vp]
         L.orc_singular_values.argtypes = [vp, ct.c_int, vp]
         L.orc_singular_values.restype = ct.c_int
-        L.orc_kitaev_S.argtypes = [vp, ct.c_int, ct.c_int, vp, ct.c_double, vp, vp, vp]
+        L.orc_kitaev_S.argtypes = [vp, ct.c_int, ct.c_int, vp, ct.c_int, ct.c_double, vp, vp, vp]
         L.orc_kitaev_S.restype = ct.c_double
-        L.orc_target.argtypes = [ct.c_int, vp, ct.c_int, ct.c_int, ct.c_int, vp, vp, vp, vp]
+        L.orc_target.argtypes = [ct.c_int, vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int, vp, vp, vp, vp]
         L.orc_init_state.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_int, ct.c_int, ct.c_int, vp]
         L.orc_gibbs_step.argtypes = [P(_Params), ct.c_int, vp, vp, vp, ct.c_uint64, ct.c_uint32,
                                      ct.c_uint32, ct.c_uint32, vp]
@@ -101,16 +102,26 @@ def _ptr(a: np.ndarray):
 
 
 class CRBM:
-    """CRBM parameters as float32 numpy arrays: W[K][C][Lw][Lw], hbias[K], vbias[C]."""
+    """CRBM parameters as float32 numpy arrays: W[K][C][Lw][Lw], hbias[K], vbias[C].
 
-    def __init__(self, W, hbias, vbias):
+    The locally connected CRBM of Sec. IV.B takes W[1+2n][K][C][Lw][Lw] and
+    hbias[1+2n][K] (bank 0 the bulk, banks 1..n the left hidden columns
+    0..n-1, banks n+1..2n the right columns L-n..L-1) with open_cols=True:
+    filter windows do not wrap across the column edge."""
+
+    def __init__(self, W, hbias, vbias, open_cols=None):
         self.W = np.ascontiguousarray(W, dtype=np.float32)
-        assert self.W.ndim == 4 and self.W.shape[2] == self.W.shape[3]
-        self.K, self.C, self.Lw = self.W.shape[0], self.W.shape[1], self.W.shape[2]
-        self.hbias = np.ascontiguousarray(hbias, dtype=np.float32).reshape(self.K)
+        assert self.W.ndim in (4, 5) and self.W.shape[-1] == self.W.shape[-2]
+        self.banks = 1 if self.W.ndim == 4 else self.W.shape[0]
+        assert self.banks % 2 == 1
+        self.n_edge = (self.banks - 1) // 2
+        self.open_cols = self.n_edge > 0 if open_cols is None else bool(open_cols)
+        self.K, self.C, self.Lw = self.W.shape[-4], self.W.shape[-3], self.W.shape[-2]
+        hshape = (self.K,) if self.W.ndim == 4 else (self.banks, self.K)
+        self.hbias = np.ascontiguousarray(hbias, dtype=np.float32).reshape(hshape)
         self.vbias = np.ascontiguousarray(vbias, dtype=np.float32).reshape(self.C)
         self._p = _Params(self.K, self.C, self.Lw, self.W.ctypes.data, self.hbias.ctypes.data,
-                          self.vbias.ctypes.data)
+                          self.vbias.ctypes.data, int(self.open_cols), self.n_edge)
 
     @property
     def p(self):
@@ -174,17 +185,17 @@ def grad(m: CRBM, x: np.ndarray, gF: np.ndarray):
     B, L = x.shape[0], x.shape[-1]
     g = np.ascontiguousarray(gF, dtype=np.float64).reshape(B)
     dW = np.zeros(m.W.shape, np.float64)
-    dhb = np.zeros(m.K, np.float64)
+    dhb = np.zeros(m.hbias.shape, np.float64)
     dvb = np.zeros(m.C, np.float64)
     lib().orc_grad(m.p, _ptr(x), B, L, _ptr(g), _ptr(dW), _ptr(dhb), _ptr(dvb))
     return dW, dhb, dvb
 
 
 # ---------------------------------------------------------------- targets
-def ising_energy(s: np.ndarray) -> int:
+def ising_energy(s: np.ndarray, open_cols: bool = False) -> int:
     s = np.ascontiguousarray(s, dtype=np.int8)
     L = s.shape[-1]
-    return int(lib().orc_ising_energy(_ptr(s), L))
+    return int(lib().orc_ising_energy(_ptr(s), L, int(open_cols)))
 
 
 def magnetization(s: np.ndarray) -> int:
@@ -192,12 +203,12 @@ def magnetization(s: np.ndarray) -> int:
     return int(lib().orc_magnetization(_ptr(s), s.shape[-1]))
 
 
-def kitaev_matrix(u: np.ndarray, J=(1.0, 1.0, 1.0)) -> np.ndarray:
+def kitaev_matrix(u: np.ndarray, J=(1.0, 1.0, 1.0), open_cols: bool = False) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.int8)
     C, L = u.shape[0], u.shape[-1]
     Jv = np.ascontiguousarray(J, dtype=np.float64)
     M = np.zeros((L * L, L * L), np.float64)
-    lib().orc_kitaev_matrix(_ptr(u), C, L, _ptr(Jv), _ptr(M))
+    lib().orc_kitaev_matrix(_ptr(u), C, L, _ptr(Jv), int(open_cols), _ptr(M))
     return M
 
 
@@ -209,7 +220,7 @@ def singular_values(A: np.ndarray):
     return sv, sweeps
 
 
-def kitaev_S(u: np.ndarray, T: float, J=(1.0, 1.0, 1.0)):
+def kitaev_S(u: np.ndarray, T: float, J=(1.0, 1.0, 1.0), open_cols: bool = False):
     """(S = -beta F, eps, E_f, C_f) of one gauge configuration u[C][L][L]."""
     u = np.ascontiguousarray(u, dtype=np.int8)
     C, L = u.shape[0], u.shape[-1]
@@ -217,21 +228,22 @@ def kitaev_S(u: np.ndarray, T: float, J=(1.0, 1.0, 1.0)):
     eps = np.zeros(L * L, np.float64)
     Ef = ct.c_double()
     Cf = ct.c_double()
-    S = lib().orc_kitaev_S(_ptr(u), C, L, _ptr(Jv), 1.0 / T, _ptr(eps), ct.byref(Ef), ct.byref(Cf))
+    S = lib().orc_kitaev_S(_ptr(u), C, L, _ptr(Jv), int(open_cols), 1.0 / T, _ptr(eps), ct.byref(Ef),
+                           ct.byref(Cf))
     return S, eps, Ef.value, Cf.value
 
 
-def target(kind: int, x: np.ndarray, T=None, J=(1.0, 1.0, 1.0)):
+def target(kind: int, x: np.ndarray, T=None, J=(1.0, 1.0, 1.0), boundary: int = 0):
     x = np.ascontiguousarray(x, dtype=np.int8)
     B, C, L = x.shape[0], x.shape[1], x.shape[-1]
     Jv = np.ascontiguousarray(J, dtype=np.float64)
     if kind == ISING:
         E = np.zeros(B, np.int64)
-        lib().orc_target(0, _ptr(x), C, B, L, _ptr(Jv), None, _ptr(E), None)
+        lib().orc_target(0, _ptr(x), C, B, L, int(boundary), _ptr(Jv), None, _ptr(E), None)
         return E
     Tv = np.ascontiguousarray(T, dtype=np.float64).reshape(B)
     S = np.zeros(B, np.float64)
-    lib().orc_target(1, _ptr(x), C, B, L, _ptr(Jv), _ptr(Tv), None, _ptr(S))
+    lib().orc_target(1, _ptr(x), C, B, L, int(boundary), _ptr(Jv), _ptr(Tv), None, _ptr(S))
     return S
 
 
@@ -257,7 +269,7 @@ class Chains:
 
     def __init__(self, m: CRBM, target_kind: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
                  burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, g0: int = 0, replica: bool = False,
-                 rbm_state=None):
+                 rbm_state=None, boundary: int = 0):
         self.m = m
         self.L = L
         self.T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
@@ -270,7 +282,7 @@ class Chains:
             self.rbm = (self.state.copy() if rbm_state is None
                         else np.array(rbm_state, dtype=np.int8, order="C", copy=True))
             assert self.rbm.shape == self.state.shape
-        self.desc = _RunDesc(target_kind, L, n, gibbs_k, burnin, g0, seed, (ct.c_double * 3)(*J))
+        self.desc = _RunDesc(target_kind, L, n, gibbs_k, burnin, g0, seed, (ct.c_double * 3)(*J), int(boundary))
         self.rec = np.zeros(n, CHAIN_DTYPE)
         self.eps = np.zeros((n, L * L), np.float64) if target_kind == 1 else None
         self.t = 0

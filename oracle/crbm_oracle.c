@@ -35,6 +35,12 @@
  *     every sweep, or a persistent CRBM replica y that the Gibbs steps advance
  *     and that is exchanged with the physical state x (App. B, parallel
  *     tempering with an exchange correction): accepted -> x <- y', y <- x.
+ *   - open boundaries (Sec. IV.B): the target drops the bonds from column
+ *     L-1 to column 0 (Ising: that nearest-neighbour bond; Kitaev: the x bond,
+ *     so chains of x and y bonds end at the left and right sides while rows
+ *     stay periodic); the locally connected CRBM keeps a shared bulk filter
+ *     bank and unshared banks for the n_edge hidden columns at each side, and
+ *     its filter windows do not wrap across the column edge.
  *   - temperature swaps of parallel tempering (Eq. (acceptance) between two
  *     physical temperatures), stream PT=4: chains sit on a ladder grid,
  *     chain g = rung * n_ladders + ladder; round r pairs rungs (q, q+1) for
@@ -124,39 +130,73 @@ ORC_API double orc_unit_uniform(uint64_t seed, uint32_t q, uint32_t t, uint32_t 
 /* ------------------------------------------------------------------ */
 /* CRBM parameters                                                     */
 /* ------------------------------------------------------------------ */
+/* Filter banks: the periodic CRBM has one bank, W[K][C][Lw][Lw], hbias[K].
+ * The locally connected CRBM of Sec. IV.B (open boundaries) has
+ * 1 + 2 n_edge banks, W[1+2n_edge][K][C][Lw][Lw], hbias[1+2n_edge][K]:
+ * bank 0 is shared by the bulk, banks 1..n_edge belong to the hidden columns
+ * 0..n_edge-1 (left side) and banks n_edge+1..2n_edge to the columns
+ * L-n_edge..L-1 (right side).  With open_cols the filter window does not wrap
+ * across the column edge: visible columns beyond it count as v = 0.  Rows stay
+ * periodic. */
 typedef struct {
     int32_t K, C, Lw;
-    const float* W;     /* [K][C][Lw][Lw] */
-    const float* hbias; /* [K] */
+    const float* W;     /* [banks][K][C][Lw][Lw] */
+    const float* hbias; /* [banks][K] */
     const float* vbias; /* [C] */
+    int32_t open_cols, n_edge;
 } orc_params;
 
 static inline int wrap(int i, int L) { int r = i % L; return r < 0 ? r + L : r; }
 
-static double Wd(const orc_params* P, int k, int c, int a, int b)
+/* filter bank of hidden column j */
+static int bank_of(const orc_params* P, int j, int L)
 {
-    return (double)P->W[((k * P->C + c) * P->Lw + a) * P->Lw + b];
+    const int ne = P->n_edge;
+    if (ne <= 0) return 0;
+    if (j < ne) return 1 + j;
+    if (j >= L - ne) return 1 + ne + (j - (L - ne));
+    return 0;
 }
 
+/* visible column reached from column j by an offset, or -1 past an open edge */
+static int column(const orc_params* P, int j, int L)
+{
+    if (P->open_cols) return (j >= 0 && j < L) ? j : -1;
+    return wrap(j, L);
+}
+
+static double Wd(const orc_params* P, int bank, int k, int c, int a, int b)
+{
+    return (double)P->W[(((size_t)bank * P->K + k) * P->C + c) * P->Lw * P->Lw + a * P->Lw + b];
+}
+
+static double hbd(const orc_params* P, int bank, int k) { return (double)P->hbias[bank * P->K + k]; }
+
 /* hidden pre-activations, Eq. (free-energy_CRBM) argument / App. B P(h|v):
- * a[k][i][j] = hb[k] + sum_{c,a,b} W[k][c][a][b] v[c][(i+a)%L][(j+b)%L]  */
+ * a[k][i][j] = hb[k] + sum_{c,a,b} W[k][c][a][b] v[c][(i+a)%L][(j+b)%L]
+ * with the bank of column j and, for open columns, no wrap in j  */
 ORC_API void orc_hidden_preact(const orc_params* P, const uint8_t* v, int L, double* a_out)
 {
     const int K = P->K, C = P->C, Lw = P->Lw;
     for (int k = 0; k < K; ++k)
         for (int i = 0; i < L; ++i)
             for (int j = 0; j < L; ++j) {
-                double s = (double)P->hbias[k];
+                const int bk = bank_of(P, j, L);
+                double s = hbd(P, bk, k);
                 for (int c = 0; c < C; ++c)
                     for (int a = 0; a < Lw; ++a)
-                        for (int b = 0; b < Lw; ++b)
-                            s += Wd(P, k, c, a, b) * (double)v[(c * L + wrap(i + a, L)) * L + wrap(j + b, L)];
+                        for (int b = 0; b < Lw; ++b) {
+                            const int jj = column(P, j + b, L);
+                            if (jj < 0) continue;
+                            s += Wd(P, bk, k, c, a, b) * (double)v[(c * L + wrap(i + a, L)) * L + jj];
+                        }
                 a_out[(k * L + i) * L + j] = s;
             }
 }
 
 /* visible pre-activations, App. B P(v|h), the exact adjoint of the above:
- * b[c][x][y] = vb[c] + sum_{k,a,b} W[k][c][a][b] h[k][(x-a)%L][(y-b)%L]  */
+ * b[c][x][y] = vb[c] + sum_{k,a,b} W[k][c][a][b] h[k][(x-a)%L][(y-b)%L]
+ * where the hidden unit at column y-b brings its own bank  */
 ORC_API void orc_visible_preact(const orc_params* P, const uint8_t* h, int L, double* b_out)
 {
     const int K = P->K, C = P->C, Lw = P->Lw;
@@ -166,8 +206,11 @@ ORC_API void orc_visible_preact(const orc_params* P, const uint8_t* h, int L, do
                 double s = (double)P->vbias[c];
                 for (int k = 0; k < K; ++k)
                     for (int a = 0; a < Lw; ++a)
-                        for (int b = 0; b < Lw; ++b)
-                            s += Wd(P, k, c, a, b) * (double)h[(k * L + wrap(x - a, L)) * L + wrap(y - b, L)];
+                        for (int b = 0; b < Lw; ++b) {
+                            const int jj = column(P, y - b, L);
+                            if (jj < 0) continue;
+                            s += Wd(P, bank_of(P, jj, L), k, c, a, b) * (double)h[(k * L + wrap(x - a, L)) * L + jj];
+                        }
                 b_out[(c * L + x) * L + y] = s;
             }
 }
@@ -219,15 +262,17 @@ ORC_API void orc_free_energy(const orc_params* P, const int8_t* x, int B, int L,
 /* Targets                                                             */
 /* ------------------------------------------------------------------ */
 /* Ising energy of Sec. III in units of J: E/J = -sum_<ij> s_i s_j, each
- * nearest-neighbour bond of the periodic square lattice counted once.  */
-ORC_API int64_t orc_ising_energy(const int8_t* s, int L)
+ * nearest-neighbour bond of the square lattice counted once; rows are
+ * periodic, columns too unless open_cols (then the bond from column L-1 to
+ * column 0 is absent).  */
+ORC_API int64_t orc_ising_energy(const int8_t* s, int L, int open_cols)
 {
     int64_t e = 0;
     for (int i = 0; i < L; ++i)
         for (int j = 0; j < L; ++j) {
             const int64_t sij = s[i * L + j];
             e -= sij * (int64_t)s[wrap(i + 1, L) * L + j];
-            e -= sij * (int64_t)s[i * L + wrap(j + 1, L)];
+            if (!(open_cols && j == L - 1)) e -= sij * (int64_t)s[i * L + wrap(j + 1, L)];
         }
     return e;
 }
@@ -244,8 +289,11 @@ ORC_API int64_t orc_magnetization(const int8_t* s, int L)
  * z -> w(i,j), x -> w(i,(j+1)%L), y -> w((i+1)%L,j).  Entry = 2 J_alpha u_alpha(r)
  * (from H = -i J sum u c_b c_w written as (i/4) sum A c c).  u is either
  * [3][L][L] (x, y, z channels) or, with C==1, the z-bond field eta alone
- * with u_x = u_y = +1.  M is N x N row-major, N = L*L, rows = black sites. */
-ORC_API void orc_kitaev_matrix(const int8_t* u, int C, int L, const double J[3], double* M)
+ * with u_x = u_y = +1.  M is N x N row-major, N = L*L, rows = black sites.
+ * open_cols (Sec. IV.B): the x bonds from column L-1 to column 0 are absent,
+ * so the chains of x and y bonds end at the left and right sides while the
+ * chains of y and z bonds stay closed. */
+ORC_API void orc_kitaev_matrix(const int8_t* u, int C, int L, const double J[3], int open_cols, double* M)
 {
     const int N = L * L;
     memset(M, 0, sizeof(double) * (size_t)N * N);
@@ -256,7 +304,7 @@ ORC_API void orc_kitaev_matrix(const int8_t* u, int C, int L, const double J[3],
             const double uy = (C == 3) ? (double)u[(1 * L + i) * L + j] : 1.0;
             const double uz = (C == 3) ? (double)u[(2 * L + i) * L + j] : (double)u[i * L + j];
             M[(size_t)r * N + r] += 2.0 * J[2] * uz;
-            M[(size_t)r * N + (i * L + wrap(j + 1, L))] += 2.0 * J[0] * ux;
+            if (!(open_cols && j == L - 1)) M[(size_t)r * N + (i * L + wrap(j + 1, L))] += 2.0 * J[0] * ux;
             M[(size_t)r * N + (wrap(i + 1, L) * L + j)] += 2.0 * J[1] * uy;
         }
 }
@@ -304,13 +352,13 @@ ORC_API int orc_singular_values(double* A, int N, double* sv)
  * summed over the N singular values of M.  Returned are S = -beta F and the
  * fermion energy E_f = -sum (eps/2) tanh(beta eps/2) and the fluctuation term
  * Cf = sum (beta eps/2)^2 / cosh^2(beta eps/2) used by the specific heat. */
-ORC_API double orc_kitaev_S(const int8_t* u, int C, int L, const double J[3], double beta,
+ORC_API double orc_kitaev_S(const int8_t* u, int C, int L, const double J[3], int open_cols, double beta,
                             double* eps_out, double* Ef_out, double* Cf_out)
 {
     const int N = L * L;
     double* M = (double*)malloc(sizeof(double) * (size_t)N * N);
     double* eps = (double*)malloc(sizeof(double) * (size_t)N);
-    orc_kitaev_matrix(u, C, L, J, M);
+    orc_kitaev_matrix(u, C, L, J, open_cols, M);
     orc_singular_values(M, N, eps);
     double S = 0.0, Ef = 0.0, Cf = 0.0;
     for (int l = 0; l < N; ++l) {
@@ -329,16 +377,16 @@ ORC_API double orc_kitaev_S(const int8_t* u, int C, int L, const double J[3], do
 }
 
 /* batched target: Ising E (units of J, exact) or Kitaev S = -beta F */
-ORC_API void orc_target(int target, const int8_t* x, int C, int B, int L, const double J[3],
+ORC_API void orc_target(int target, const int8_t* x, int C, int B, int L, int open_cols, const double J[3],
                         const double* T, int64_t* E_out, double* S_out)
 {
 #pragma omp parallel for schedule(dynamic)
     for (int b = 0; b < B; ++b) {
         const int8_t* s = x + (size_t)b * C * L * L;
         if (target == 0) {
-            if (E_out) E_out[b] = orc_ising_energy(s, L);
+            if (E_out) E_out[b] = orc_ising_energy(s, L, open_cols);
         } else {
-            if (S_out) S_out[b] = orc_kitaev_S(s, C, L, J, 1.0 / T[b], NULL, NULL, NULL);
+            if (S_out) S_out[b] = orc_kitaev_S(s, C, L, J, open_cols, 1.0 / T[b], NULL, NULL, NULL);
         }
     }
 }
@@ -395,6 +443,7 @@ typedef struct {
     uint32_t g0;
     uint64_t seed;
     double J[3];
+    int32_t boundary; /* target lattice: 0 periodic, 1 open columns (Sec. IV.B) */
 } orc_run_desc;
 
 /* record of the current state: cached F and target, zeroed sums */
@@ -414,9 +463,9 @@ ORC_API void orc_chain_init(const orc_params* P, const orc_run_desc* D, const do
             spins_to_visible(s, C, L, v);
             R->F = free_energy_v(P, v, L, a);
             if (D->target != 1) {
-                R->E = orc_ising_energy(s, L);
+                R->E = orc_ising_energy(s, L, D->boundary);
             } else {
-                R->S = orc_kitaev_S(s, C, L, D->J, 1.0 / T[g], eps ? eps + (size_t)g * L * L : NULL, &R->Ef,
+                R->S = orc_kitaev_S(s, C, L, D->J, D->boundary, 1.0 / T[g], eps ? eps + (size_t)g * L * L : NULL, &R->Ef,
                                     &R->Cf);
             }
         }
@@ -472,10 +521,10 @@ ORC_API void orc_run(const orc_params* P, const orc_run_desc* D, const double* T
                 int64_t Ep = 0;
                 double Sp = 0, Efp = 0, Cfp = 0;
                 if (D->target != 1) {
-                    Ep = orc_ising_energy(sp, L);
+                    Ep = orc_ising_energy(sp, L, D->boundary);
                     logr = -beta * D->J[0] * (double)(Ep - R->E) + (Fp - R->F);
                 } else {
-                    Sp = orc_kitaev_S(sp, C, L, D->J, beta, epsp, &Efp, &Cfp);
+                    Sp = orc_kitaev_S(sp, C, L, D->J, D->boundary, beta, epsp, &Efp, &Cfp);
                     logr = (Sp - R->S) + (Fp - R->F);
                 }
                 const double lu = log(orc_mh_uniform(D->seed, t, gid));
@@ -608,15 +657,17 @@ ORC_API void orc_tempering_swap(const orc_run_desc* D, int C, const double* T, i
 /* dF/dW[k][c][a][b] = -sum_ij sigma(a[k][i][j]) v[c][(i+a)%L][(j+b)%L]  */
 /* dF/dhb[k]         = -sum_ij sigma(a[k][i][j])                         */
 /* dF/dvb[c]         = -sum_ij v[c][i][j]                                */
-/* out = sum_n g_n dF(x_n)/dtheta                                        */
+/* out = sum_n g_n dF(x_n)/dtheta; with several banks, hidden column j    */
+/* contributes to the bank that owns it; dW, dhb have the banks' layout.  */
 /* ------------------------------------------------------------------ */
 ORC_API void orc_grad(const orc_params* P, const int8_t* x, int B, int L, const double* gF,
                       double* dW, double* dhb, double* dvb)
 {
     const int K = P->K, C = P->C, Lw = P->Lw, n = L * L;
+    const int nb = 1 + 2 * (P->n_edge > 0 ? P->n_edge : 0);
     const int nW = K * C * Lw * Lw;
-    memset(dW, 0, sizeof(double) * (size_t)nW);
-    memset(dhb, 0, sizeof(double) * (size_t)K);
+    memset(dW, 0, sizeof(double) * (size_t)nb * nW);
+    memset(dhb, 0, sizeof(double) * (size_t)nb * K);
     memset(dvb, 0, sizeof(double) * (size_t)C);
     uint8_t* v = (uint8_t*)malloc((size_t)C * n);
     double* a = (double*)malloc(sizeof(double) * (size_t)K * n);
@@ -628,12 +679,16 @@ ORC_API void orc_grad(const orc_params* P, const int8_t* x, int B, int L, const 
             for (int i = 0; i < L; ++i)
                 for (int j = 0; j < L; ++j) {
                     const double sg = sigmoid(a[(k * L + i) * L + j]);
-                    dhb[k] -= g * sg;
+                    const int bk = bank_of(P, j, L);
+                    dhb[bk * K + k] -= g * sg;
                     for (int c = 0; c < C; ++c)
                         for (int aa = 0; aa < Lw; ++aa)
-                            for (int bb = 0; bb < Lw; ++bb)
-                                dW[((k * C + c) * Lw + aa) * Lw + bb] -=
-                                    g * sg * (double)v[(c * L + wrap(i + aa, L)) * L + wrap(j + bb, L)];
+                            for (int bb = 0; bb < Lw; ++bb) {
+                                const int jj = column(P, j + bb, L);
+                                if (jj < 0) continue;
+                                dW[(size_t)bk * nW + ((k * C + c) * Lw + aa) * Lw + bb] -=
+                                    g * sg * (double)v[(c * L + wrap(i + aa, L)) * L + jj];
+                            }
                 }
         for (int c = 0; c < C; ++c) {
             double nvc = 0.0;

@@ -23,21 +23,25 @@ import numpy as np
 
 @dataclass
 class Filters:
-    W: np.ndarray      # float32 [K][C][Lw][Lw]
-    hbias: np.ndarray  # float32 [K]
+    W: np.ndarray      # float32 [K][C][Lw][Lw], or [banks][K][C][Lw][Lw] for a locally connected CRBM
+    hbias: np.ndarray  # float32 [K], or [banks][K]
     vbias: np.ndarray  # float32 [C]
 
     @property
     def K(self):
-        return self.W.shape[0]
+        return self.W.shape[-4]
 
     @property
     def C(self):
-        return self.W.shape[1]
+        return self.W.shape[-3]
 
     @property
     def Lw(self):
-        return self.W.shape[2]
+        return self.W.shape[-1]
+
+    @property
+    def banks(self):
+        return 1 if self.W.ndim == 4 else self.W.shape[0]
 
 
 def random_filters(K: int, C: int, Lw: int, std: float, seed: int = 0) -> Filters:
@@ -136,3 +140,19 @@ def ar1_series(n: int, length: int, phi: float, seed: int = 0) -> np.ndarray:
     for i in range(1, length):
         x[:, i] = phi * x[:, i - 1] + e[:, i]
     return x
+
+
+def lcrbm_from_crbm(f: Filters, n_edge: int, edge_std: float = 0.0, seed: int = 0) -> Filters:
+    """Filter banks of a locally connected CRBM started from a periodic CRBM
+    (Sec. IV.B starts the open-boundary machine from the periodic one): bank 0
+    and the 2 n_edge edge banks are copies of f, the edge banks plus
+    N(0, edge_std) noise."""
+    assert f.W.ndim == 4
+    nb = 1 + 2 * n_edge
+    rng = np.random.default_rng(seed)
+    W = np.repeat(f.W[None], nb, 0).astype(np.float32)
+    hb = np.repeat(f.hbias.reshape(1, -1), nb, 0).astype(np.float32)
+    if edge_std > 0 and n_edge > 0:
+        W[1:] += rng.normal(0.0, edge_std, W[1:].shape).astype(np.float32)
+        hb[1:] += rng.normal(0.0, edge_std, hb[1:].shape).astype(np.float32)
+    return Filters(W, hb, f.vbias.copy())
