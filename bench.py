@@ -40,9 +40,9 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 # after any change to them `traffic` is reported as null until re-measured.
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
                   "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": "f537ca5418cd28debb81b32de26f2d6b83ab483672a43d565c7ce913413e9ff3",
+MEASURED_TRAFFIC = {"sources_sha256": "80205e6462c712bec90a0822fbb0c82d7094703415dbe2f490e6fbe6757c6c47",
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
-                    "fetch_kib": 9312.9, "fetch_scale": 2.0, "write_kib": 20114.7, "write_scale": 1.0}
+                    "fetch_kib": 9312.4, "fetch_scale": 2.0, "write_kib": 20117.8, "write_scale": 1.0}
 
 
 def kernel_sources_sha256():
@@ -239,10 +239,20 @@ def autocorrelation_times(sizes=(16, 32, 64, 128), chains=64, burn=1000, record=
             def go():
                 res["r"] = api.autocorrelation(ring, max_lag, start=start)
             ms = _timed(go)
-            _, tau, win = (t.cpu().numpy() for t in res["r"])
+            cov, tau, win = (t.cpu().numpy() for t in res["r"])
             st = job.stats()
             ok = win > 0
+            # pooled estimate: the chains are independent replicas at one temperature, so
+            # their autocovariances are averaged before the window is chosen
+            rho = cov.mean(0) / cov.mean(0)[0]
+            tp, wp = 0.5, -1
+            for t in range(1, max_lag + 1):
+                tp += rho[t]
+                if t >= 6.0 * tp:
+                    wp = t
+                    break
             out[f"{tname}_L{L}"] = {
+                "tau_int_pooled": float(tp), "window_pooled": wp,
                 "tau_int_mean": float(tau[ok].mean()) if ok.any() else None,
                 "tau_int_sem": float(tau[ok].std(ddof=1) / np.sqrt(ok.sum())) if ok.sum() > 1 else None,
                 "chains_with_window": int(ok.sum()), "chains": chains, "recorded_sweeps": count,
@@ -317,6 +327,39 @@ def kitaev_training_and_transfer(L=6, L_big=12, T=0.3):
         job.run(4)
         st = job.stats()
         out[f"acceptance_L{L_big}_{name}"] = float(st["n_acc"].sum() / st["sweeps"].sum())
+        job.close()
+    out["open_boundary"] = kitaev_open_boundary(pre, L_big, T)
+    return out
+
+
+def kitaev_open_boundary(periodic, L, T, n_edge=3):
+    """Sec. IV.B at L=12, open columns: a locally connected CRBM (3 unshared
+    filter banks per side) started from the periodic pre-trained CRBM,
+    retrained on 256 samples it drew itself (40 exchange-corrected sweeps,
+    6 epochs of Alg. 1); exchange acceptance with the refreshed replica (128
+    chains, 4 sweeps) of the periodic CRBM, the initial and the retrained
+    LCRBM, and the loss of Eq. (loss) on the samples."""
+    import torch
+
+    from paper_2008_05401_amd import api, train
+    t0 = time.perf_counter()
+    init, fin, x = train.kitaev_open_transfer(periodic, L, T, n_edge=n_edge, n_phys=256, sweeps=40, epochs=6)
+    torch.cuda.synchronize()
+    out = {"L": L, "T": T, "n_edge": n_edge, "retrain_s": time.perf_counter() - t0}
+    nlp = train.kitaev_nlp(T, boundary=1)
+    nx = nlp(x)
+    out["loss_open_samples"] = {"initial": train.full_loss_nlp(x, nx, init.W, init.hbias, init.vbias),
+                                "retrained": train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)}
+    cases = (("periodic_crbm", api.CRBMParams(periodic.W, periodic.hbias, periodic.vbias)),
+             ("lcrbm_initial", api.CRBMParams(init.W, init.hbias, init.vbias)),
+             ("lcrbm_retrained", api.CRBMParams(fin.W, fin.hbias, fin.vbias)))
+    for name, p in cases:
+        job = api.Job(p, api.KITAEV, L, np.full(128, T), seed=6, boundary=1)
+        job.run(1)
+        ms = _timed(lambda: job.run(3)) / 3
+        st = job.stats()
+        out[f"acceptance_{name}"] = float(st["n_acc"].sum() / st["sweeps"].sum())
+        out[f"ms_per_sweep_{name}"] = ms
         job.close()
     return out
 

@@ -76,12 +76,22 @@ typedef enum {
 typedef enum { CRBM_ISING = 0, CRBM_KITAEV = 1, CRBM_GIBBS = 2 } crbm_target;
 
 /* CRBM parameters theta = (W, hbias, vbias); all device, float32.
- * K in [1, 64], C in {1, 3}, Lw in [1, 8] and Lw <= L. */
+ * K in [1, 64], C in {1, 3}, Lw in [1, 8] and Lw <= L.
+ * The locally connected CRBM of Sec. IV.B (open boundaries) sets n_edge >= 1:
+ * W and hbias then hold 1 + 2 n_edge filter banks; bank 0 is shared by the bulk
+ * hidden columns, banks 1..n_edge belong to the hidden columns 0..n_edge-1
+ * (left side) and banks n_edge+1..2 n_edge to the columns L-n_edge..L-1 (right
+ * side); 0 <= n_edge <= 4 and 2 n_edge <= L.  open_cols = 1 stops the filter
+ * windows at the column edge (visible columns past it count as v = 0) instead
+ * of wrapping; rows always wrap.  A zero-initialised tail (open_cols = n_edge
+ * = 0) is the periodic CRBM of Eq. (energy_CRBM). */
 typedef struct {
     int32_t K, C, Lw;
-    const float* W;     /* device [K][C][Lw][Lw] */
-    const float* hbias; /* device [K] */
+    const float* W;     /* device [banks][K][C][Lw][Lw], banks = 1 + 2 n_edge */
+    const float* hbias; /* device [banks][K] */
     const float* vbias; /* device [C] */
+    int32_t open_cols;  /* 0: windows wrap in both directions; 1: open columns */
+    int32_t n_edge;     /* unshared banks per side */
 } crbm_params;
 
 /* One job: n_chains chains on an L x L lattice.
@@ -108,7 +118,9 @@ typedef struct {
     int32_t burnin_sweeps; /* sweeps with index < burnin are not measured */
     int32_t init_state;    /* 1: crbm_init fills `state` from the INIT stream */
     uint32_t chain_offset; /* Philox chain index of chain 0 */
-    int32_t reserved;
+    int32_t boundary;      /* target lattice: 0 periodic; 1 open columns (Sec. IV.B):
+                              the Ising bond / the Kitaev x bond from column L-1
+                              to column 0 is absent, rows stay periodic */
     uint64_t seed;         /* Philox key */
     double J[3];           /* Ising: J[0] is J. Kitaev: J_x, J_y, J_z */
     const double* T;       /* device [n_chains] temperatures */
@@ -214,14 +226,14 @@ CRBM_API crbm_status crbm_destroy(crbm_ctx* ctx);
 CRBM_API crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x, int32_t B, int32_t L,
                              double* F_out, void* stream);
 
-/* Target of B states x[B][C][L][L] (device).
+/* Target of B states x[B][C][L][L] (device); boundary as in crbm_batch_desc.
  * CRBM_ISING (C must be 1): E_out[B] = E/J = -sum_<ij> s_i s_j (device int32,
  *   exact); S_out ignored (may be NULL).
  * CRBM_KITAEV (C = 1 or 3): S_out[B] = sum_lambda log 2cosh(eps_lambda/(2 T[b]))
  *   (device FP64) over the N = L^2 singular values of M; T is device [B];
  *   E_out ignored. L <= 12 for Kitaev. */
 CRBM_API crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L,
-                          const double J[3] /* host */, const double* T, int32_t* E_out,
+                          int32_t boundary, const double J[3] /* host */, const double* T, int32_t* E_out,
                           double* S_out, void* stream);
 
 /* Vector-Jacobian product of F (the backward of the loss of Eq. (loss)):
@@ -229,6 +241,9 @@ CRBM_API crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, i
  *   dF/dW[k][c][a][b'] = -sum_ij sigmoid(a[k][i][j]) v[c][(i+a)%L][(j+b')%L]
  *   dF/dhbias[k]       = -sum_ij sigmoid(a[k][i][j])
  *   dF/dvbias[c]       = -sum_ij v[c][i][j].
+ * With filter banks, dW and dhbias have the banks' layout and a bank's sums
+ * run over the hidden columns it owns (and, with open_cols, over the visible
+ * columns inside the lattice only).
  * x[B][C][L][L] +-1 device; gF[B] float32 device; outputs float32 device,
  * overwritten.  Per-sample sums in FP32 terms / FP64 accumulation, the sum
  * over samples in FP64 in a fixed order (deterministic). `workspace` is a

@@ -23,13 +23,14 @@ class CRBMError(RuntimeError):
 
 class crbm_params(ct.Structure):
     _fields_ = [("K", ct.c_int32), ("C", ct.c_int32), ("Lw", ct.c_int32),
-                ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p)]
+                ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p),
+                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32)]
 
 
 class crbm_batch_desc(ct.Structure):
     _fields_ = [("target", ct.c_int32), ("L", ct.c_int32), ("n_chains", ct.c_int32),
                 ("gibbs_k", ct.c_int32), ("burnin_sweeps", ct.c_int32), ("init_state", ct.c_int32),
-                ("chain_offset", ct.c_uint32), ("reserved", ct.c_int32), ("seed", ct.c_uint64),
+                ("chain_offset", ct.c_uint32), ("boundary", ct.c_int32), ("seed", ct.c_uint64),
                 ("J", ct.c_double * 3), ("T", ct.c_void_p), ("state", ct.c_void_p),
                 ("rbm_state", ct.c_void_p), ("workspace", ct.c_void_p), ("workspace_bytes", ct.c_size_t)]
 
@@ -74,7 +75,8 @@ def load(path: str = LIB_PATH):
     L.crbm_sweeps_done.restype = ct.c_int64
     L.crbm_destroy.argtypes = [vp]
     L.crbm_free_energy.argtypes = [P(crbm_params), vp, ct.c_int32, ct.c_int32, vp, vp]
-    L.target_energy.argtypes = [ct.c_int32, vp, ct.c_int32, ct.c_int32, ct.c_int32, P(ct.c_double), vp, vp, vp, vp]
+    L.target_energy.argtypes = [ct.c_int32, vp, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, P(ct.c_double), vp, vp,
+                                vp, vp]
     L.crbm_grad_workspace_size.argtypes = [P(crbm_params), ct.c_int32]
     L.crbm_grad_workspace_size.restype = ct.c_size_t
     L.crbm_grad.argtypes = [P(crbm_params), vp, ct.c_int32, ct.c_int32, vp, vp, vp, vp, vp, ct.c_size_t, vp]
@@ -148,9 +150,9 @@ def crbm_free_energy(params, x_ptr, B, L, F_ptr, stream):
     check(load().crbm_free_energy(ct.byref(params), x_ptr, B, L, F_ptr, stream))
 
 
-def target_energy(target, x_ptr, B, C, L, J, T_ptr, E_ptr, S_ptr, stream):
+def target_energy(target, x_ptr, B, C, L, boundary, J, T_ptr, E_ptr, S_ptr, stream):
     Jv = (ct.c_double * 3)(*J)
-    check(load().target_energy(target, x_ptr, B, C, L, Jv, T_ptr, E_ptr, S_ptr, stream))
+    check(load().target_energy(target, x_ptr, B, C, L, int(boundary), Jv, T_ptr, E_ptr, S_ptr, stream))
 
 
 def crbm_grad_workspace_size(params, B) -> int:

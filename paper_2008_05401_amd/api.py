@@ -36,27 +36,38 @@ def _dev(device=None):
 
 
 class CRBMParams:
-    """Filters W[K][C][Lw][Lw], hbias[K], vbias[C] as float32 device tensors."""
+    """Filters W[K][C][Lw][Lw], hbias[K], vbias[C] as float32 device tensors.
 
-    def __init__(self, W, hbias, vbias, device=None):
+    The locally connected CRBM of Sec. IV.B passes W[1+2n][K][C][Lw][Lw] and
+    hbias[1+2n][K] (bank 0 for the bulk hidden columns, banks 1..n for the
+    left columns 0..n-1, banks n+1..2n for the right columns L-n..L-1);
+    open_cols (default: on when there are edge banks) stops the filter windows
+    at the column edge."""
+
+    def __init__(self, W, hbias, vbias, device=None, open_cols=None):
         dev = _dev(device)
         self.W = torch.as_tensor(np.asarray(W, np.float32) if not torch.is_tensor(W) else W,
                                  dtype=torch.float32, device=dev).contiguous()
+        assert self.W.dim() in (4, 5) and self.W.shape[-1] == self.W.shape[-2]
+        self.banks = 1 if self.W.dim() == 4 else int(self.W.shape[0])
+        assert self.banks % 2 == 1
+        self.n_edge = (self.banks - 1) // 2
+        self.open_cols = self.n_edge > 0 if open_cols is None else bool(open_cols)
+        self.K, self.C, self.Lw = int(self.W.shape[-4]), int(self.W.shape[-3]), int(self.W.shape[-1])
+        hshape = (self.K,) if self.W.dim() == 4 else (self.banks, self.K)
         self.hbias = torch.as_tensor(np.asarray(hbias, np.float32) if not torch.is_tensor(hbias) else hbias,
-                                     dtype=torch.float32, device=dev).contiguous().reshape(-1)
+                                     dtype=torch.float32, device=dev).contiguous().reshape(hshape)
         self.vbias = torch.as_tensor(np.asarray(vbias, np.float32) if not torch.is_tensor(vbias) else vbias,
                                      dtype=torch.float32, device=dev).contiguous().reshape(-1)
-        assert self.W.dim() == 4 and self.W.shape[2] == self.W.shape[3]
-        self.K, self.C, self.Lw = int(self.W.shape[0]), int(self.W.shape[1]), int(self.W.shape[2])
-        assert self.hbias.numel() == self.K and self.vbias.numel() == self.C
+        assert self.vbias.numel() == self.C
 
     @classmethod
-    def from_filters(cls, f, device=None):
-        return cls(f.W, f.hbias, f.vbias, device)
+    def from_filters(cls, f, device=None, open_cols=None):
+        return cls(f.W, f.hbias, f.vbias, device, open_cols)
 
     def struct(self) -> C.crbm_params:
         return C.crbm_params(self.K, self.C, self.Lw, self.W.data_ptr(), self.hbias.data_ptr(),
-                             self.vbias.data_ptr())
+                             self.vbias.data_ptr(), int(self.open_cols), self.n_edge)
 
 
 class Job:
@@ -70,7 +81,7 @@ class Job:
 
     def __init__(self, params: CRBMParams, target: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
                  burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, chain_offset: int = 0, stream=None,
-                 replica: bool = False, rbm_state=None):
+                 replica: bool = False, rbm_state=None, boundary: int = 0):
         dev = params.W.device
         self.params = params
         self.target = int(target)
@@ -101,7 +112,7 @@ class Job:
         self._p = params.struct()
         self._stream = stream
         self._desc = C.crbm_batch_desc(self.target, self.L, n, int(gibbs_k), int(burnin), init,
-                                       int(chain_offset), 0, int(seed), (C.ct.c_double * 3)(*J),
+                                       int(chain_offset), int(boundary), int(seed), (C.ct.c_double * 3)(*J),
                                        self.T.data_ptr(), self.state.data_ptr(),
                                        self.rbm_state.data_ptr() if self.rbm_state is not None else None, 0, 0)
         ws = C.crbm_workspace_size(self._p, self._desc)
@@ -204,22 +215,23 @@ def free_energy(params: CRBMParams, x: torch.Tensor, stream=None) -> torch.Tenso
     return F
 
 
-def ising_energy(x: torch.Tensor, stream=None) -> torch.Tensor:
+def ising_energy(x: torch.Tensor, stream=None, boundary: int = 0) -> torch.Tensor:
     x = x.to(dtype=torch.int8).contiguous()
     B, L = int(x.shape[0]), int(x.shape[-1])
     E = torch.empty(B, dtype=torch.int32, device=x.device)
-    C.target_energy(ISING, x.data_ptr(), B, 1, L, (1.0, 1.0, 1.0), None, E.data_ptr(), None,
+    C.target_energy(ISING, x.data_ptr(), B, 1, L, boundary, (1.0, 1.0, 1.0), None, E.data_ptr(), None,
                     _stream_ptr(stream))
     return E
 
 
-def kitaev_weight(u: torch.Tensor, T, J=(1.0, 1.0, 1.0), stream=None) -> torch.Tensor:
+def kitaev_weight(u: torch.Tensor, T, J=(1.0, 1.0, 1.0), stream=None, boundary: int = 0) -> torch.Tensor:
     u = u.to(dtype=torch.int8).contiguous()
     B, Cc, L = int(u.shape[0]), int(u.shape[1]), int(u.shape[-1])
     Tt = torch.as_tensor(np.asarray(T, np.float64).reshape(-1), device=u.device).contiguous()
     assert Tt.numel() == B
     S = torch.empty(B, dtype=torch.float64, device=u.device)
-    C.target_energy(KITAEV, u.data_ptr(), B, Cc, L, J, Tt.data_ptr(), None, S.data_ptr(), _stream_ptr(stream))
+    C.target_energy(KITAEV, u.data_ptr(), B, Cc, L, boundary, J, Tt.data_ptr(), None, S.data_ptr(),
+                    _stream_ptr(stream))
     return S
 
 
@@ -246,18 +258,19 @@ class CRBMFreeEnergy(torch.autograd.Function):
     (None, dW, dhbias, dvbias) with d = sum_b grad_out[b] dF_b/dtheta."""
 
     @staticmethod
-    def forward(ctx, x, W, hbias, vbias):
-        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device)
+    def forward(ctx, x, W, hbias, vbias, open_cols=None):
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=open_cols)
         ctx.save_for_backward(x, W, hbias, vbias)
+        ctx.open_cols = open_cols
         return free_energy(p, x)
 
     @staticmethod
     def backward(ctx, gout):
         x, W, hbias, vbias = ctx.saved_tensors
-        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device)
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=ctx.open_cols)
         dW, dhb, dvb = grad(p, x, gout.to(torch.float32))
-        return None, dW, dhb, dvb
+        return None, dW, dhb.reshape(hbias.shape), dvb, None
 
 
-def crbm_free_energy_fn(x, W, hbias, vbias):
-    return CRBMFreeEnergy.apply(x, W, hbias, vbias)
+def crbm_free_energy_fn(x, W, hbias, vbias, open_cols=None):
+    return CRBMFreeEnergy.apply(x, W, hbias, vbias, open_cols)

@@ -50,6 +50,18 @@ crbm_status check_params(const crbm_params* p)
     if (p->C != 1 && p->C != 3) return fail(CRBM_EINVAL, "C=%d must be 1 or 3", p->C);
     if (p->Lw < 1 || p->Lw > 8) return fail(CRBM_EINVAL, "Lw=%d outside [1,8]", p->Lw);
     if (!p->W || !p->hbias || !p->vbias) return fail(CRBM_EINVAL, "W, hbias and vbias must be device pointers");
+    if (p->open_cols != 0 && p->open_cols != 1) return fail(CRBM_EINVAL, "open_cols=%d must be 0 or 1", p->open_cols);
+    if (p->n_edge < 0 || p->n_edge > 4) return fail(CRBM_EINVAL, "n_edge=%d outside [0,4]", p->n_edge);
+    return CRBM_OK;
+}
+
+int banks_of(const crbm_params* p) { return 1 + 2 * p->n_edge; }
+
+crbm_status check_lattice(const crbm_params* p, int L)
+{
+    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
+    if (p->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", p->Lw, L);
+    if (2 * p->n_edge > L) return fail(CRBM_EINVAL, "2*n_edge=%d larger than L=%d", 2 * p->n_edge, L);
     return CRBM_OK;
 }
 
@@ -88,8 +100,9 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (!d) return fail(CRBM_EINVAL, "desc is NULL");
     if (d->target != CRBM_ISING && d->target != CRBM_KITAEV && d->target != CRBM_GIBBS)
         return fail(CRBM_EINVAL, "unknown target %d", d->target);
-    if (d->L < 1 || d->L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", d->L);
-    if (p->Lw > d->L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", p->Lw, d->L);
+    st = check_lattice(p, d->L);
+    if (st != CRBM_OK) return st;
+    if (d->boundary != 0 && d->boundary != 1) return fail(CRBM_EINVAL, "boundary=%d must be 0 or 1", d->boundary);
     if (d->n_chains < 1) return fail(CRBM_EINVAL, "n_chains=%d must be >= 1", d->n_chains);
     if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
@@ -98,7 +111,8 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->target == CRBM_GIBBS && d->rbm_state)
         return fail(CRBM_EINVAL, "a persistent CRBM replica needs a physical target (got CRBM_GIBBS)");
     Plan pl{};
-    if (d->target != CRBM_KITAEV && p->C == 1 && ising_fast_supported(p->K, p->Lw, d->L)) {
+    const bool plain = p->open_cols == 0 && p->n_edge == 0 && d->boundary == 0;
+    if (plain && d->target != CRBM_KITAEV && p->C == 1 && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
         pl.nt = ising_fast_threads(d->L);
         pl.rows = ising_fast_rows(d->L);
@@ -109,7 +123,7 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
         pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
         // the Kitaev eigen-step is latency-bound: one 16-wave workgroup per chain from N = 16 on
         if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = 1024;
-        pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target);
+        pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target, banks_of(p));
     }
     if (pl.lds > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "job needs %zu bytes of LDS per chain (limit %zu)", pl.lds, kLdsLimit);
@@ -250,6 +264,9 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.burnin = desc->burnin_sweeps;
     j.chain_offset = desc->chain_offset;
     j.init_state = desc->init_state;
+    j.open_cols = params->open_cols;
+    j.n_edge = params->n_edge;
+    j.boundary = desc->boundary;
     hipError_t e = hipMemcpyAsync(c->job_dev, &c->job, sizeof(JobDev), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -262,7 +279,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     P.block_begin[1] = desc->n_chains;
     P.n_jobs = 1;
     P.mode = MODE_INIT;
-    const size_t lds = init_lds(params->K, params->C, params->Lw, desc->L, desc->target);
+    const size_t lds = init_lds(params->K, params->C, params->Lw, desc->L, desc->target, banks_of(params));
     if (lds > kLdsLimit) {
         delete c;
         return fail(CRBM_EUNSUPPORTED, "initialisation needs %zu bytes of LDS", lds);
@@ -375,27 +392,28 @@ crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x, int32_t
     crbm_status st = check_params(params);
     if (st != CRBM_OK) return st;
     if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
-    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
-    if (params->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", params->Lw, L);
+    st = check_lattice(params, L);
+    if (st != CRBM_OK) return st;
     if (B == 0) return CRBM_OK;
     if (!x || !F_out) return fail(CRBM_EINVAL, "x and F_out must be device pointers");
-    if (free_energy_lds(params->K, params->C, params->Lw, L) > kLdsLimit)
+    if (free_energy_lds(params->K, params->C, params->Lw, L, banks_of(params)) > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "free energy needs too much LDS for L=%d", L);
-    hipError_t e = launch_free_energy(params->W, params->hbias, params->vbias, params->K, params->C, params->Lw, x, B, L,
-                                      F_out, (hipStream_t)stream);
+    hipError_t e = launch_free_energy(params->W, params->hbias, params->vbias, params->K, params->C, params->Lw,
+                                      params->open_cols, params->n_edge, x, B, L, F_out, (hipStream_t)stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_free_energy launch");
 }
 
-crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L, const double J[3],
-                          const double* T, int32_t* E_out, double* S_out, void* stream)
+crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L, int32_t boundary,
+                          const double J[3], const double* T, int32_t* E_out, double* S_out, void* stream)
 {
     if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
     if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
+    if (boundary != 0 && boundary != 1) return fail(CRBM_EINVAL, "boundary=%d must be 0 or 1", boundary);
     if (target == CRBM_ISING) {
         if (C != 1) return fail(CRBM_EINVAL, "Ising needs C=1 (got %d)", C);
         if (B == 0) return CRBM_OK;
         if (!x || !E_out) return fail(CRBM_EINVAL, "x and E_out must be device pointers");
-        hipError_t e = launch_ising_energy(x, B, L, E_out, (hipStream_t)stream);
+        hipError_t e = launch_ising_energy(x, B, L, boundary, E_out, (hipStream_t)stream);
         return e == hipSuccess ? CRBM_OK : hip_fail(e, "target_energy launch");
     }
     if (target == CRBM_KITAEV) {
@@ -404,7 +422,7 @@ crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C,
         if (!J) return fail(CRBM_EINVAL, "J must point to 3 host doubles");
         if (B == 0) return CRBM_OK;
         if (!x || !S_out || !T) return fail(CRBM_EINVAL, "x, T and S_out must be device pointers");
-        hipError_t e = launch_kitaev_weight(x, B, C, L, J[0], J[1], J[2], T, S_out, (hipStream_t)stream);
+        hipError_t e = launch_kitaev_weight(x, B, C, L, boundary, J[0], J[1], J[2], T, S_out, (hipStream_t)stream);
         return e == hipSuccess ? CRBM_OK : hip_fail(e, "target_energy launch");
     }
     return fail(CRBM_EINVAL, "unknown target %d", target);
@@ -413,7 +431,8 @@ crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C,
 size_t crbm_grad_workspace_size(const crbm_params* params, int32_t B)
 {
     if (check_params(params) != CRBM_OK || B < 0) return 0;
-    const size_t P = (size_t)params->K * params->C * params->Lw * params->Lw + params->K + params->C;
+    const size_t P = (size_t)banks_of(params) * ((size_t)params->K * params->C * params->Lw * params->Lw + params->K) +
+                     params->C;
     return round_up(std::max<size_t>(1, (size_t)B) * P * sizeof(double), 256);
 }
 
@@ -423,17 +442,18 @@ crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int
     crbm_status st = check_params(params);
     if (st != CRBM_OK) return st;
     if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
-    if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
-    if (params->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", params->Lw, L);
+    st = check_lattice(params, L);
+    if (st != CRBM_OK) return st;
     if (!dW || !dhbias || !dvbias) return fail(CRBM_EINVAL, "gradient outputs must be device pointers");
     if (B > 0 && (!x || !gF)) return fail(CRBM_EINVAL, "x and gF must be device pointers");
     const size_t need = crbm_grad_workspace_size(params, B);
     if (!workspace || workspace_bytes < need)
         return fail(CRBM_EBUDGET, "grad workspace of %zu bytes, %zu needed", workspace_bytes, need);
-    if (grad_lds(params->K, params->C, params->Lw, L) > kLdsLimit)
+    if (grad_lds(params->K, params->C, params->Lw, L, banks_of(params)) > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "gradient needs too much LDS for L=%d", L);
-    hipError_t e = launch_grad(params->W, params->hbias, params->K, params->C, params->Lw, x, B, L, gF,
-                               (double*)workspace, dW, dhbias, dvbias, (hipStream_t)stream);
+    hipError_t e = launch_grad(params->W, params->hbias, params->K, params->C, params->Lw, params->open_cols,
+                               params->n_edge, x, B, L, gF, (double*)workspace, dW, dhbias, dvbias,
+                               (hipStream_t)stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_grad launch");
 }
 

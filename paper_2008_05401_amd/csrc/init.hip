@@ -9,10 +9,10 @@
 
 namespace crbm {
 
-__host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, int target)
+__host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, int target, int banks)
 {
     size_t o = 64 * 8;
-    o += ((size_t)K * C * LW * LW + K + C) * 4;
+    o += ((size_t)banks * (K * C * LW * LW + K) + C) * 4;
     o = (o + 15) / 16 * 16;
     o += (size_t)C * L * L;
     o = (o + 15) / 16 * 16;
@@ -28,13 +28,15 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     const JobDev& J = *P.jobs[jb];
     const int g = (int)blockIdx.x - P.block_begin[jb];
     if (g >= J.n_chains) return;
-    const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L, nW = K * C * LW * LW;
+    const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L;
+    const int nb = 1 + 2 * J.n_edge, nW = nb * K * C * LW * LW;
+    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge};
     const int tid = threadIdx.x, NT = blockDim.x;
     double* red = (double*)smem;
     float* Ws = (float*)(smem + 64 * 8);
     float* hbs = Ws + nW;
-    float* vbs = hbs + K;
-    size_t o = 64 * 8 + ((size_t)nW + K + C) * 4;
+    float* vbs = hbs + nb * K;
+    size_t o = 64 * 8 + ((size_t)nW + nb * K + C) * 4;
     o = (o + 15) / 16 * 16;
     uint8_t* v = smem + o;
     o += (size_t)C * LL;
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     double* kit = (double*)(smem + o);
 
     for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
-    for (int q = tid; q < K; q += NT) hbs[q] = J.hb[q];
+    for (int q = tid; q < nb * K; q += NT) hbs[q] = J.hb[q];
     for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
     const uint32_t gid = J.chain_offset + (uint32_t)g;
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
@@ -61,15 +63,15 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
         for (int q = tid; q < C * LL; q += NT) v[q] = state[q] > 0;
     }
     __syncthreads();
-    const double F = free_energy_block(Ws, hbs, vbs, v, K, C, LW, L, red);
+    const double F = free_energy_block(Ws, hbs, vbs, v, G, red);
     long long E = 0, M = 0;
     KitaevOut ko{0.0, 0.0, 0.0};
     if (J.target != 1) {
-        ising_em_block(v, L, (long long*)red, E, M);
+        ising_em_block(v, L, J.boundary, (long long*)red, E, M);
     } else {
         const int N = LL;
         double* A = kit;
-        ko = kitaev_weight_block(v, C, L, J.J0, J.J1, J.J2, 1.0 / J.T[g], A, A + N * (N + 1) / 2,
+        ko = kitaev_weight_block(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], A, A + N * (N + 1) / 2,
                                  A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N, A + N * (N + 1) / 2 + 3 * N,
                                  red, A);
         // singular values of the initial state, kept for temperature swaps
@@ -87,7 +89,10 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     }
 }
 
-size_t init_lds(int K, int C, int LW, int L, int target) { return init_lds_bytes(K, C, LW, L, target); }
+size_t init_lds(int K, int C, int LW, int L, int target, int banks)
+{
+    return init_lds_bytes(K, C, LW, L, target, banks);
+}
 
 hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s)
 {

@@ -28,9 +28,10 @@ struct KitaevOut {
 
 // LDS needs: A[N(N+1)/2], d[N], e[N], hv[N], p[N] doubles and `red` (>= 16 doubles).
 // v: 0/1 bytes of the proposal, C channels ([3][L][L] = x,y,z bonds, or [1][L][L] = z bonds).
-__device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double Jx, double Jy, double Jz,
-                                         double beta, double* A, double* d, double* e, double* hv, double* p,
-                                         double* red, double* eps_out = nullptr)
+// open_cols (Sec. IV.B): the x bonds from column L-1 to column 0 are absent.
+__device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
+                                         double Jz, double beta, double* A, double* d, double* e, double* hv,
+                                         double* p, double* red, double* eps_out = nullptr)
 {
     const int N = L * L;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -41,19 +42,21 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
     __syncthreads();
     for (int w = tid; w < N; w += nt) {
         const int i = w / L, j = w - (w / L) * L;
-        // black neighbours of w(i,j): b(i,j) via z, b(i,j-1) via x, b(i-1,j) via y
+        // black neighbours of w(i,j): b(i,j) via z, b(i,j-1) via x (none at an
+        // open left side), b(i-1,j) via y
         int bn[3];
         bn[0] = w;
-        bn[1] = i * L + (j == 0 ? L - 1 : j - 1);
+        bn[1] = j == 0 ? (open_cols ? -1 : i * L + L - 1) : i * L + j - 1;
         bn[2] = (i == 0 ? L - 1 : i - 1) * L + j;
         for (int nb = 0; nb < 3; ++nb) {
             const int b = bn[nb];
+            if (b < 0) continue;
             const int bi = b / L, bj = b - (b / L) * L;
             // white neighbours of b(bi,bj) and the matrix entries M[b][w']
             int wn[3];
             double wv[3];
             wn[0] = b;
-            wn[1] = bi * L + (bj + 1 == L ? 0 : bj + 1);
+            wn[1] = bj + 1 == L ? (open_cols ? -1 : bi * L) : bi * L + bj + 1;
             wn[2] = (bi + 1 == L ? 0 : bi + 1) * L + bj;
             const double vz = C == 3 ? (v[2 * N + b] ? 1.0 : -1.0) : (v[b] ? 1.0 : -1.0);
             const double vx = C == 3 ? (v[0 * N + b] ? 1.0 : -1.0) : 1.0;
@@ -71,6 +74,7 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, double 
             if (dup) continue;
             for (int t = 0; t < 3; ++t) {
                 const int w2 = wn[t];
+                if (w2 < 0) continue;
                 bool dupw = false;
                 for (int s = 0; s < t; ++s) dupw |= (wn[s] == w2);
                 if (dupw || w2 > w) continue;

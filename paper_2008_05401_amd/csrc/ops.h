@@ -6,15 +6,17 @@
 
 namespace crbm {
 
-size_t free_energy_lds(int K, int C, int LW, int L);
-hipError_t launch_free_energy(const float* W, const float* hb, const float* vb, int K, int C, int LW, const int8_t* x,
-                              int B, int L, double* F, hipStream_t s);
-hipError_t launch_ising_energy(const int8_t* x, int B, int L, int32_t* E, hipStream_t s);
+// `open`, `ne`: the locally connected CRBM (windows stop at the column edge,
+// 1 + 2 ne filter banks); open_cols: the open-column target lattice
+size_t free_energy_lds(int K, int C, int LW, int L, int banks);
+hipError_t launch_free_energy(const float* W, const float* hb, const float* vb, int K, int C, int LW, int open, int ne,
+                              const int8_t* x, int B, int L, double* F, hipStream_t s);
+hipError_t launch_ising_energy(const int8_t* x, int B, int L, int open_cols, int32_t* E, hipStream_t s);
 size_t kitaev_weight_lds(int C, int L);
-hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, double Jx, double Jy, double Jz, const double* T,
-                                double* S, hipStream_t s);
-size_t grad_lds(int K, int C, int LW, int L);
-hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, const int8_t* x, int B, int L,
-                       const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
+hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_cols, double Jx, double Jy, double Jz,
+                                const double* T, double* S, hipStream_t s);
+size_t grad_lds(int K, int C, int LW, int L, int banks);
+hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, int open, int ne, const int8_t* x, int B,
+                       int L, const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
 
 }  // namespace crbm

@@ -1,42 +1,56 @@
 // ops.hip -- stand-alone kernels of the C ABI: batched CRBM free energy,
-// target energies (Ising E, Kitaev S) and the backward of F.
+// target energies (Ising E, Kitaev S) and the backward of F.  The CRBM may be
+// the locally connected one of Sec. IV.B: `banks` = 1 + 2 ne filter banks
+// ([banks][K][C][LW][LW], hidden biases [banks][K]), bank 0 for the bulk
+// columns, banks 1..ne for the hidden columns 0..ne-1 and ne+1..2ne for
+// L-ne..L-1; with `open` the windows stop at the column edge.
 #include "device_common.h"
 #include "kitaev_eig.h"
 #include "ops.h"
 
 namespace crbm {
 
+__device__ __forceinline__ int bank_of_col(int j, int L, int ne)
+{
+    return j < ne ? 1 + j : (j >= L - ne ? 1 + ne + (j - (L - ne)) : 0);
+}
+
 // ---------------------------------------------------------------------------
 // F(x_b) of Eq. (free-energy_CRBM), FP64 terms and sums; one workgroup per state.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void free_energy_kernel(const float* __restrict__ W, const float* __restrict__ hb,
-                                                          const float* __restrict__ vb, int K, int C, int LW,
-                                                          const int8_t* __restrict__ x, int L, double* __restrict__ F)
+                                                          const float* __restrict__ vb, int K, int C, int LW, int open,
+                                                          int ne, const int8_t* __restrict__ x, int L,
+                                                          double* __restrict__ F)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int LL = L * L, nW = K * C * LW * LW;
+    const int LL = L * L, nW = K * C * LW * LW, nb = 1 + 2 * ne;
     double* red = (double*)smem;
     double* Wd = red + 64;
-    double* hbd = Wd + nW;
-    uint8_t* v = (uint8_t*)(hbd + K);
+    double* hbd = Wd + nb * nW;
+    uint8_t* v = (uint8_t*)(hbd + nb * K);
     const int8_t* xs = x + (size_t)blockIdx.x * C * LL;
-    for (int q = threadIdx.x; q < nW; q += blockDim.x) Wd[q] = (double)W[q];
-    for (int q = threadIdx.x; q < K; q += blockDim.x) hbd[q] = (double)hb[q];
+    for (int q = threadIdx.x; q < nb * nW; q += blockDim.x) Wd[q] = (double)W[q];
+    for (int q = threadIdx.x; q < nb * K; q += blockDim.x) hbd[q] = (double)hb[q];
     for (int q = threadIdx.x; q < C * LL; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
     double fl = 0.0;
     for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        double acc = hbd[k];
+        const int bk = bank_of_col(j, L, ne);
+        double acc = hbd[bk * K + k];
         for (int c = 0; c < C; ++c)
             for (int a = 0; a < LW; ++a) {
                 int ia = i + a;
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
-                const double* wr = Wd + ((k * C + c) * LW + a) * LW;
+                const double* wr = Wd + bk * nW + ((k * C + c) * LW + a) * LW;
                 for (int b = 0; b < LW; ++b) {
                     int jb = j + b;
-                    if (jb >= L) jb -= L;
+                    if (jb >= L) {
+                        if (open) break;
+                        jb -= L;
+                    }
                     acc += row[jb] ? wr[b] : 0.0;
                 }
             }
@@ -47,23 +61,25 @@ __global__ __launch_bounds__(256) void free_energy_kernel(const float* __restric
     if (threadIdx.x == 0) F[blockIdx.x] = tot;
 }
 
-size_t free_energy_lds(int K, int C, int LW, int L)
+size_t free_energy_lds(int K, int C, int LW, int L, int banks)
 {
-    return 64 * 8 + (size_t)(K * C * LW * LW + K) * 8 + (size_t)C * L * L + 16;
+    return 64 * 8 + (size_t)banks * (K * C * LW * LW + K) * 8 + (size_t)C * L * L + 16;
 }
 
-hipError_t launch_free_energy(const float* W, const float* hb, const float* vb, int K, int C, int LW, const int8_t* x,
-                              int B, int L, double* F, hipStream_t s)
+hipError_t launch_free_energy(const float* W, const float* hb, const float* vb, int K, int C, int LW, int open, int ne,
+                              const int8_t* x, int B, int L, double* F, hipStream_t s)
 {
-    hipLaunchKernelGGL(free_energy_kernel, dim3(B), dim3(256), free_energy_lds(K, C, LW, L), s, W, hb, vb, K, C, LW, x,
-                       L, F);
+    hipLaunchKernelGGL(free_energy_kernel, dim3(B), dim3(256), free_energy_lds(K, C, LW, L, 1 + 2 * ne), s, W, hb, vb,
+                       K, C, LW, open, ne, x, L, F);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Ising E/J = -sum_<ij> s_i s_j, exact int32; one workgroup per state.
+// Ising E/J = -sum_<ij> s_i s_j, exact int32; one workgroup per state.  With
+// open_cols the bond from column L-1 to column 0 is absent.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void ising_energy_kernel(const int8_t* __restrict__ x, int L, int32_t* __restrict__ E)
+__global__ __launch_bounds__(256) void ising_energy_kernel(const int8_t* __restrict__ x, int L, int open_cols,
+                                                           int32_t* __restrict__ E)
 {
     __shared__ int red[16];
     const int LL = L * L;
@@ -71,24 +87,25 @@ __global__ __launch_bounds__(256) void ising_energy_kernel(const int8_t* __restr
     int el = 0;
     for (int q = threadIdx.x; q < LL; q += blockDim.x) {
         const int i = q / L, j = q - i * L;
-        el -= (int)s[q] * ((int)s[(i + 1 == L ? 0 : i + 1) * L + j] + (int)s[i * L + (j + 1 == L ? 0 : j + 1)]);
+        const int right = (open_cols && j + 1 == L) ? 0 : (int)s[i * L + (j + 1 == L ? 0 : j + 1)];
+        el -= (int)s[q] * ((int)s[(i + 1 == L ? 0 : i + 1) * L + j] + right);
     }
     const int tot = block_sum(el, red);
     if (threadIdx.x == 0) E[blockIdx.x] = tot;
 }
 
-hipError_t launch_ising_energy(const int8_t* x, int B, int L, int32_t* E, hipStream_t s)
+hipError_t launch_ising_energy(const int8_t* x, int B, int L, int open_cols, int32_t* E, hipStream_t s)
 {
-    hipLaunchKernelGGL(ising_energy_kernel, dim3(B), dim3(256), 0, s, x, L, E);
+    hipLaunchKernelGGL(ising_energy_kernel, dim3(B), dim3(256), 0, s, x, L, open_cols, E);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Kitaev S = sum log 2cosh(eps / 2T), FP64; one workgroup per configuration.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, double Jx,
-                                                            double Jy, double Jz, const double* __restrict__ T,
-                                                            double* __restrict__ S)
+__global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, int open_cols,
+                                                            double Jx, double Jy, double Jz,
+                                                            const double* __restrict__ T, double* __restrict__ S)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = L * L;
@@ -98,7 +115,7 @@ __global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __res
     const int8_t* xs = x + (size_t)blockIdx.x * C * N;
     for (int q = threadIdx.x; q < C * N; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
-    const KitaevOut o = kitaev_weight_block(v, C, L, Jx, Jy, Jz, 1.0 / T[blockIdx.x], A, A + N * (N + 1) / 2,
+    const KitaevOut o = kitaev_weight_block(v, C, L, open_cols, Jx, Jy, Jz, 1.0 / T[blockIdx.x], A, A + N * (N + 1) / 2,
                                             A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
                                             A + N * (N + 1) / 2 + 3 * N, red);
     if (threadIdx.x == 0) S[blockIdx.x] = o.S;
@@ -106,11 +123,11 @@ __global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __res
 
 size_t kitaev_weight_lds(int C, int L) { return 64 * 8 + kitaev_lds_bytes(L) + (size_t)C * L * L + 16; }
 
-hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, double Jx, double Jy, double Jz, const double* T,
-                                double* S, hipStream_t s)
+hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_cols, double Jx, double Jy, double Jz,
+                                const double* T, double* S, hipStream_t s)
 {
     hipLaunchKernelGGL(kitaev_weight_kernel, dim3(B), dim3(L * L >= 16 ? 1024 : 256), kitaev_weight_lds(C, L), s, x, C, L,
-                       Jx, Jy, Jz, T, S);
+                       open_cols, Jx, Jy, Jz, T, S);
     return hipGetLastError();
 }
 
@@ -119,32 +136,39 @@ hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, double Jx,
 // hidden unit (float32 pre-activation, FP64 sigmoid, stored as float), then one
 // thread per parameter p forms g_b dF(x_b)/dtheta_p in FP64 into
 // part[b][p].  Stage 2: out[p] = sum_b part[b][p] in sample order.
+// Parameters are ordered W[banks][K][C][LW][LW], hbias[banks][K], vbias[C];
+// a bank's gradient sums over the hidden columns that bank owns.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, const float* __restrict__ hb, int K,
-                                                   int C, int LW, const int8_t* __restrict__ x, int L,
-                                                   const float* __restrict__ gF, double* __restrict__ part)
+                                                   int C, int LW, int open, int ne, const int8_t* __restrict__ x,
+                                                   int L, const float* __restrict__ gF, double* __restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int LL = L * L, nW = K * C * LW * LW, P = nW + K + C;
+    const int nb = 1 + 2 * ne;
+    const int LL = L * L, nW = K * C * LW * LW, P = nb * (nW + K) + C;
     float* Ws = (float*)smem;
-    float* sg = Ws + nW;
+    float* sg = Ws + nb * nW;
     uint8_t* v = (uint8_t*)(sg + K * LL);
     const int8_t* xs = x + (size_t)blockIdx.x * C * LL;
-    for (int q = threadIdx.x; q < nW; q += blockDim.x) Ws[q] = W[q];
+    for (int q = threadIdx.x; q < nb * nW; q += blockDim.x) Ws[q] = W[q];
     for (int q = threadIdx.x; q < C * LL; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
     for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        float acc = hb[k];
+        const int bk = bank_of_col(j, L, ne);
+        float acc = hb[bk * K + k];
         for (int c = 0; c < C; ++c)
             for (int a = 0; a < LW; ++a) {
                 int ia = i + a;
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
-                const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+                const float* wr = Ws + bk * nW + ((k * C + c) * LW + a) * LW;
                 for (int b = 0; b < LW; ++b) {
                     int jb = j + b;
-                    if (jb >= L) jb -= L;
+                    if (jb >= L) {
+                        if (open) break;
+                        jb -= L;
+                    }
                     acc = fmaf(wr[b], (float)row[jb], acc);
                 }
             }
@@ -155,8 +179,9 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
     double* out = part + (size_t)blockIdx.x * P;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         double s = 0.0;
-        if (p < nW) {
-            const int b = p % LW, a = (p / LW) % LW, c = (p / (LW * LW)) % C, k = p / (C * LW * LW);
+        if (p < nb * nW) {
+            const int bank = p / nW, pw = p - bank * nW;
+            const int b = pw % LW, a = (pw / LW) % LW, c = (pw / (LW * LW)) % C, k = pw / (C * LW * LW);
             const float* sk = sg + k * LL;
             for (int i = 0; i < L; ++i) {
                 int ia = i + a;
@@ -164,16 +189,22 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
                 const uint8_t* row = v + (c * L + ia) * L;
                 const float* srow = sk + i * L;
                 for (int j = 0; j < L; ++j) {
+                    if (bank_of_col(j, L, ne) != bank) continue;
                     int jb = j + b;
-                    if (jb >= L) jb -= L;
+                    if (jb >= L) {
+                        if (open) continue;
+                        jb -= L;
+                    }
                     s += row[jb] ? (double)srow[j] : 0.0;
                 }
             }
-        } else if (p < nW + K) {
-            const float* sk = sg + (p - nW) * LL;
-            for (int q = 0; q < LL; ++q) s += (double)sk[q];
+        } else if (p < nb * (nW + K)) {
+            const int q0 = p - nb * nW, bank = q0 / K, k = q0 - bank * K;
+            const float* sk = sg + k * LL;
+            for (int q = 0; q < LL; ++q)
+                if (bank_of_col(q % L, L, ne) == bank) s += (double)sk[q];
         } else {
-            const uint8_t* vc = v + (p - nW - K) * LL;
+            const uint8_t* vc = v + (p - nb * (nW + K)) * LL;
             for (int q = 0; q < LL; ++q) s += (double)vc[q];
         }
         out[p] = -gb * s;
@@ -193,22 +224,24 @@ __global__ __launch_bounds__(256) void grad_stage2(const double* __restrict__ pa
     else dvb[p - nW - K] = (float)s;
 }
 
-size_t grad_lds(int K, int C, int LW, int L)
+size_t grad_lds(int K, int C, int LW, int L, int banks)
 {
-    return (size_t)(K * C * LW * LW) * 4 + (size_t)K * L * L * 4 + (size_t)C * L * L + 16;
+    return (size_t)banks * (K * C * LW * LW) * 4 + (size_t)K * L * L * 4 + (size_t)C * L * L + 16;
 }
 
-hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, const int8_t* x, int B, int L,
-                       const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s)
+hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, int open, int ne, const int8_t* x, int B,
+                       int L, const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s)
 {
-    const int P = K * C * LW * LW + K + C;
+    const int nb = 1 + 2 * ne;
+    const int P = nb * (K * C * LW * LW + K) + C;
     if (B > 0) {
-        hipLaunchKernelGGL(grad_stage1, dim3(B), dim3(256), grad_lds(K, C, LW, L), s, W, hb, K, C, LW, x, L, gF, part);
+        hipLaunchKernelGGL(grad_stage1, dim3(B), dim3(256), grad_lds(K, C, LW, L, nb), s, W, hb, K, C, LW, open, ne, x,
+                           L, gF, part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(grad_stage2, dim3((P + 255) / 256), dim3(256), 0, s, part, B, P, K * C * LW * LW, K, dW, dhb,
-                       dvb);
+    hipLaunchKernelGGL(grad_stage2, dim3((P + 255) / 256), dim3(256), 0, s, part, B, P, nb * K * C * LW * LW, nb * K,
+                       dW, dhb, dvb);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ struct GenericLds {
     int off_red, off_W, off_hb, off_vb, off_dah, off_dav, off_v, off_h, off_kit, total;
 };
 
-__host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, int L, int target)
+__host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, int L, int target, int banks)
 {
     GenericLds g;
     const int LL = L * L;
@@ -35,13 +35,13 @@ __host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, i
     g.off_red = o;
     o += 64 * 8;
     g.off_W = o;
-    o += al(K * C * LW * LW * 4, 16);
+    o += al(banks * K * C * LW * LW * 4, 16);
     g.off_hb = o;
-    o += al(K * 4, 16);
+    o += al(banks * K * 4, 16);
     g.off_vb = o;
     o += al(C * 4, 16);
     g.off_dah = o;
-    o += al(K * 4, 16);
+    o += al(banks * K * 4, 16);
     g.off_dav = o;
     o += al(C * 4, 16);
     g.off_v = o;
@@ -65,8 +65,10 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     if (g >= J.n_chains) return;
 
     const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L;
+    const int nb = 1 + 2 * J.n_edge;
+    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge};
     const int tid = threadIdx.x;
-    const GenericLds lay = generic_lds_layout(K, C, LW, L, J.target);
+    const GenericLds lay = generic_lds_layout(K, C, LW, L, J.target, nb);
     double* red = (double*)(smem + lay.off_red);
     long long* redi = (long long*)(smem + lay.off_red);
     float* Ws = (float*)(smem + lay.off_W);
@@ -79,20 +81,26 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     double* kit = (double*)(smem + lay.off_kit);
 
     const int nW = K * C * LW * LW;
-    for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
-    for (int q = tid; q < K; q += NT) hbs[q] = J.hb[q];
+    for (int q = tid; q < nb * nW; q += NT) Ws[q] = J.W[q];
+    for (int q = tid; q < nb * K; q += NT) hbs[q] = J.hb[q];
     for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
     __syncthreads();
-    // error bounds of the float32 pre-activations (recursive fma summation)
-    for (int k = tid; k < K; k += NT) {
-        float s = fabsf(hbs[k]);
-        for (int q = 0; q < C * LW * LW; ++q) s += fabsf(Ws[k * C * LW * LW + q]);
-        dAh[k] = gamma_f32(C * LW * LW + 2) * s * 1.001f;
+    // error bounds of the float32 pre-activations (recursive fma summation):
+    // per bank and hidden channel; a visible unit sums terms of several banks,
+    // so its bound takes the largest |W| over the banks term by term
+    for (int bk = tid; bk < nb * K; bk += NT) {
+        float s = fabsf(hbs[bk]);
+        for (int q = 0; q < C * LW * LW; ++q) s += fabsf(Ws[bk * C * LW * LW + q]);
+        dAh[bk] = gamma_f32(C * LW * LW + 2) * s * 1.001f;
     }
     for (int c = tid; c < C; c += NT) {
         float s = fabsf(vbs[c]);
         for (int k = 0; k < K; ++k)
-            for (int q = 0; q < LW * LW; ++q) s += fabsf(Ws[(k * C + c) * LW * LW + q]);
+            for (int q = 0; q < LW * LW; ++q) {
+                float m = 0.0f;
+                for (int b = 0; b < nb; ++b) m = fmaxf(m, fabsf(Ws[b * nW + (k * C + c) * LW * LW + q]));
+                s += m;
+            }
         dAv[c] = gamma_f32(K * LW * LW + 2) * s * 1.001f;
     }
 
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     long long Mcur = 0;
     if (ising) {
         long long Ed;
-        ising_em_block(vcur0, L, redi, Ed, Mcur);
+        ising_em_block(vcur0, L, J.boundary, redi, Ed, Mcur);
     } else {
         __syncthreads();
     }
@@ -152,11 +160,11 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
                     const int q = 4 * gi + w;
                     if (q < nh) {
                         const int k = q / LL, rr = q - k * LL, i = rr / L, j = rr - i * L;
-                        const float a = preact_hidden_f(Ws, hbs, vs, C, LW, L, k, i, j);
+                        const float a = preact_hidden_f(Ws, hbs, vs, G, k, i, j);
                         bool near;
-                        bool on = bernoulli_fast(a, word_of(r, w), dAh[k], near);
+                        bool on = bernoulli_fast(a, word_of(r, w), dAh[G.bank(j) * K + k], near);
                         if (near) {
-                            on = bernoulli_exact(preact_hidden_d(Ws, hbs, vs, K, C, LW, L, k, i, j), word_of(r, w));
+                            on = bernoulli_exact(preact_hidden_d(Ws, hbs, vs, G, k, i, j), word_of(r, w));
                             ++nre;
                         }
                         h[q] = on;
@@ -173,11 +181,11 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
                     const int q = 4 * gi + w;
                     if (q < nv) {
                         const int c = q / LL, rr = q - c * LL, x = rr / L, y = rr - x * L;
-                        const float b = preact_visible_f(Ws, vbs, h, K, C, LW, L, c, x, y);
+                        const float b = preact_visible_f(Ws, vbs, h, G, c, x, y);
                         bool near;
                         bool on = bernoulli_fast(b, word_of(r, w), dAv[c], near);
                         if (near) {
-                            on = bernoulli_exact(preact_visible_d(Ws, vbs, h, K, C, LW, L, c, x, y), word_of(r, w));
+                            on = bernoulli_exact(preact_visible_d(Ws, vbs, h, G, c, x, y), word_of(r, w));
                             ++nre;
                         }
                         vd[q] = on;
@@ -188,14 +196,14 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             src = dst;
         }
         const uint8_t* vp = vb3 + src * C * LL;
-        const double Fp = free_energy_block(Ws, hbs, vbs, vp, K, C, LW, L, red);
+        const double Fp = free_energy_block(Ws, hbs, vbs, vp, G, red);
         long long Ep = 0, Mp = 0;
         KitaevOut ko{0.0, 0.0, 0.0};
-        if (ising) ising_em_block(vp, L, redi, Ep, Mp);
+        if (ising) ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
         else {
             double* A = kit;
             const int N = LL;
-            ko = kitaev_weight_block(vp, C, L, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
+            ko = kitaev_weight_block(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
                                      A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
                                      A + N * (N + 1) / 2 + 3 * N, red, kit);
         }
@@ -264,9 +272,9 @@ template __global__ void sweep_generic_kernel<1024>(SweepLaunch);
 template __global__ void sweep_generic_kernel<256>(SweepLaunch);
 template __global__ void sweep_generic_kernel<64>(SweepLaunch);
 
-size_t generic_lds_bytes(int K, int C, int LW, int L, int target)
+size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks)
 {
-    return (size_t)generic_lds_layout(K, C, LW, L, target).total;
+    return (size_t)generic_lds_layout(K, C, LW, L, target, banks).total;
 }
 
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)

@@ -18,6 +18,9 @@ lattice, on the GPU, for the Ising and the Kitaev targets.
     random gauge configurations with their exact weights, then samples of the
     physical distribution are drawn with the pre-trained CRBM through the
     exchange-corrected sampler and the training is finished on them.
+* Open boundaries (Sec. IV.B): the locally connected CRBM starts from the
+  filters of a periodic CRBM (every bank a copy) and is retrained on samples
+  of the open-boundary target drawn with itself.
 """
 from __future__ import annotations
 
@@ -51,9 +54,9 @@ def ising_nlp(T: float):
     return lambda x: api.ising_energy(x).to(torch.float64) / T
 
 
-def kitaev_nlp(T: float, J=(1.0, 1.0, 1.0)):
+def kitaev_nlp(T: float, J=(1.0, 1.0, 1.0), boundary: int = 0):
     """-log P of the Kitaev gauge field at T up to a constant: -S."""
-    return lambda x: -api.kitaev_weight(x, np.full(int(x.shape[0]), T), J)
+    return lambda x: -api.kitaev_weight(x, np.full(int(x.shape[0]), T), J, boundary=boundary)
 
 
 @dataclass
@@ -72,10 +75,13 @@ def _params_of(f, dev):
 
 def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K: int = 8, Lw: int = 5,
                epochs: int = 30, batch: int = 20, lr: float = 1e-3, ub: int = 200, gibbs_k: int = 1, seed: int = 0,
-               train_size: int = None, log_every: int = 0, init=None, replay: bool = True) -> TrainResult:
+               train_size: int = None, log_every: int = 0, init=None, replay: bool = True,
+               open_cols=None) -> TrainResult:
     """Alg. 1 on physical states x_phys [n][C][L][L] with nlp_phys = -log P(x_phys) + const.
     `nlp_fn(x)` evaluates the same for replay-buffer states; `init` optionally
-    continues from filters (W, hbias, vbias) instead of the Alg. 1 initialisation."""
+    continues from filters (W, hbias, vbias) instead of the Alg. 1 initialisation
+    (filter banks of a locally connected CRBM included; open_cols as in
+    api.CRBMParams)."""
     dev = x_phys.device
     C = int(x_phys.shape[1])
     L = int(x_phys.shape[-1])
@@ -98,7 +104,7 @@ def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K
     for ep in range(epochs):
         if replay:
             # UPDATE BUFFER: k Gibbs steps of the current CRBM from the previous new states
-            p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev)
+            p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev, open_cols=open_cols)
             job = api.Job(p, api.GIBBS, L, np.full(ub, T), seed=seed + 1000 + ep, gibbs_k=gibbs_k, state=buf)
             job.run(1)
             buf = job.state.clone()
@@ -112,7 +118,7 @@ def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K
         perm = torch.randperm(x_tot.shape[0], generator=gen).to(dev)
         for s0 in range(0, x_tot.shape[0] - batch + 1, batch):
             idx = perm[s0:s0 + batch]
-            F = api.crbm_free_energy_fn(x_tot[idx], W, hb, vb)
+            F = api.crbm_free_energy_fn(x_tot[idx], W, hb, vb, open_cols)
             diff = n_tot[idx] - F
             Cc = diff.mean()
             loss = ((diff - Cc) ** 2).mean()
@@ -134,9 +140,9 @@ def full_loss(x: torch.Tensor, E: torch.Tensor, T: float, W, hb, vb) -> float:
     return full_loss_nlp(x, E.to(torch.float64) / T, W, hb, vb)
 
 
-def full_loss_nlp(x: torch.Tensor, nlp: torch.Tensor, W, hb, vb) -> float:
+def full_loss_nlp(x: torch.Tensor, nlp: torch.Tensor, W, hb, vb, open_cols=None) -> float:
     """The loss of Eq. (loss) with its optimal constant over the whole set."""
-    p = api.CRBMParams(W, hb, vb, device=W.device)
+    p = api.CRBMParams(W, hb, vb, device=W.device, open_cols=open_cols)
     F = api.free_energy(p, x)
     diff = nlp.to(torch.float64) - F
     return float(((diff - diff.mean()) ** 2).mean())
@@ -168,3 +174,42 @@ def kitaev_pretrain_and_train(L: int, T: float, K: int = 8, Lw: int = 3, n_rando
     fin = train_crbm(x, nlp(x), nlp, T, K=K, Lw=Lw, epochs=epochs, batch=20, lr=lr, ub=128, seed=seed + 1,
                      init=(pre.W, pre.hbias, pre.vbias))
     return pre, fin, x, acc, xr
+
+
+def sample_states(params, target: int, L: int, T: float, n: int, sweeps: int, seed: int, J=(1.0, 1.0, 1.0),
+                  boundary: int = 0):
+    """n states of the physical target drawn by the exchange-corrected sampler
+    (persistent CRBM replicas) after `sweeps` sweeps; returns (states,
+    exchange acceptance)."""
+    job = api.Job(params, target, L, np.full(n, T), seed=seed, J=J, replica=True, boundary=boundary)
+    done = 0
+    while done < sweeps:
+        b = min(50, sweeps - done)
+        job.run(b)
+        done += b
+    x = job.state.clone()
+    st = job.stats()
+    acc = float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
+    job.close()
+    return x, acc
+
+
+def kitaev_open_transfer(periodic: TrainResult, L: int, T: float, n_edge: int = 3, n_phys: int = 256,
+                         sweeps: int = 40, epochs: int = 6, lr: float = 1e-3, seed: int = 0, J=(1.0, 1.0, 1.0)):
+    """Sec. IV.B: a locally connected CRBM for the open-boundary Kitaev target.
+    Every filter bank starts as a copy of the periodic CRBM; samples of the
+    open-boundary target at size L are drawn with it (exchange-corrected) and
+    Alg. 1 retrains all banks on them.  Returns (initial LCRBM, retrained
+    LCRBM, samples)."""
+    dev = periodic.W.device
+    nb = 1 + 2 * n_edge
+    W0 = periodic.W.detach().unsqueeze(0).repeat(nb, 1, 1, 1, 1).contiguous()
+    hb0 = periodic.hbias.detach().reshape(1, -1).repeat(nb, 1).contiguous()
+    vb0 = periodic.vbias.detach().clone()
+    init = TrainResult(W0, hb0, vb0, [], 0)
+    p = api.CRBMParams(W0, hb0, vb0, device=dev)
+    x, _ = sample_states(p, api.KITAEV, L, T, n_phys, sweeps, seed + 21, J=J, boundary=1)
+    nlp = kitaev_nlp(T, J, boundary=1)
+    fin = train_crbm(x, nlp(x), nlp, T, K=int(W0.shape[1]), Lw=int(W0.shape[-1]), epochs=epochs, batch=20, lr=lr,
+                     ub=128, seed=seed + 3, init=(W0, hb0, vb0))
+    return init, fin, x

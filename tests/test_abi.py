@@ -43,15 +43,15 @@ def test_version(lib):
     assert "gfx950" in _lib.crbm_version()
 
 
-def _params(K=4, C=1, Lw=3, ptr=0x1000):
+def _params(K=4, C=1, Lw=3, ptr=0x1000, open_cols=0, n_edge=0):
     from paper_2008_05401_amd import _lib
-    return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr)
+    return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr, open_cols, n_edge)
 
 
-def _desc(target=0, L=8, n=4, gk=1, rbm=None):
+def _desc(target=0, L=8, n=4, gk=1, rbm=None, boundary=0):
     from paper_2008_05401_amd import _lib
     return _lib.crbm_batch_desc(target=target, L=L, n_chains=n, gibbs_k=gk, burnin_sweeps=0, init_state=1,
-                                chain_offset=0, reserved=0, seed=0, J=(ct.c_double * 3)(1, 1, 1), T=0x1000,
+                                chain_offset=0, boundary=boundary, seed=0, J=(ct.c_double * 3)(1, 1, 1), T=0x1000,
                                 state=0x1000, rbm_state=rbm, workspace=0x1000, workspace_bytes=1 << 20)
 
 
@@ -70,6 +70,13 @@ def test_workspace_size_validation(lib):
     assert _lib.crbm_workspace_size(_params(), _desc(target=2, rbm=0x1000)) == 0  # replica needs a target
     assert _lib.crbm_workspace_size(_params(C=3), _desc(target=2)) > 0            # Gibbs-only chains, C = 3
     assert _lib.crbm_workspace_size(_params(), _desc(rbm=0x1000)) > 0
+    # locally connected CRBM and open boundaries
+    assert _lib.crbm_workspace_size(_params(open_cols=1, n_edge=3), _desc(L=6, boundary=1)) > 0
+    assert _lib.crbm_workspace_size(_params(open_cols=1, n_edge=3), _desc(L=5)) == 0   # 2 n_edge > L
+    assert _lib.crbm_workspace_size(_params(n_edge=5), _desc(L=16)) == 0               # n_edge > 4
+    assert _lib.crbm_workspace_size(_params(open_cols=2), _desc()) == 0
+    assert _lib.crbm_workspace_size(_params(), _desc(boundary=2)) == 0
+    assert _lib.crbm_workspace_size(_params(C=3, n_edge=1, open_cols=1), _desc(target=1, L=6, boundary=1)) > 0
     # Kitaev keeps the singular values of every chain: 4 chains x 36 doubles more
     kit = _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=6))
     assert kit >= _lib.crbm_workspace_size(_params(), _desc(L=6)) + 4 * 36 * 8
@@ -95,9 +102,10 @@ def test_other_entry_points_validate(lib):
     assert L.crbm_free_energy(ct.byref(p), None, -1, 8, None, None) == _lib.CRBM_EINVAL
     assert L.crbm_free_energy(ct.byref(p), None, 0, 8, None, None) == _lib.CRBM_OK   # empty batch
     J = (ct.c_double * 3)(1, 1, 1)
-    assert L.target_energy(0, None, 1, 3, 8, J, None, None, None, None) == _lib.CRBM_EINVAL
-    assert L.target_energy(7, None, 1, 1, 8, J, None, None, None, None) == _lib.CRBM_EINVAL
-    assert L.target_energy(1, None, 1, 3, 13, J, None, None, None, None) == _lib.CRBM_EUNSUPPORTED
+    assert L.target_energy(0, None, 1, 3, 8, 0, J, None, None, None, None) == _lib.CRBM_EINVAL
+    assert L.target_energy(7, None, 1, 1, 8, 0, J, None, None, None, None) == _lib.CRBM_EINVAL
+    assert L.target_energy(1, None, 1, 3, 13, 0, J, None, None, None, None) == _lib.CRBM_EUNSUPPORTED
+    assert L.target_energy(0, None, 1, 1, 8, 2, J, None, None, None, None) == _lib.CRBM_EINVAL   # boundary
     assert L.crbm_grad_workspace_size(ct.byref(p), 10) >= 10 * (36 + 4 + 1) * 8
     assert L.crbm_grad(ct.byref(p), None, 1, 8, None, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EINVAL
     assert L.crbm_grad(ct.byref(p), 0x1000, 1, 8, 0x1000, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EBUDGET

@@ -89,3 +89,23 @@ def test_kitaev_pretraining_and_self_samples(mods):
     assert np.isfinite(lf_x) and lf_x < 1.1 * lp_x, (lp_x, lf_x)
     # the replay buffer ran three-channel Gibbs-only chains
     assert fin.W.shape == (8, 3, 3, 3)
+
+
+def test_lcrbm_open_boundary_transfer(mods):
+    # Sec. IV.B: the locally connected CRBM starts from the periodic CRBM (every
+    # bank a copy) and is retrained on open-boundary samples it drew itself
+    api, train = mods
+    L, T = 4, 0.3
+    pre, _, _, _, _ = train.kitaev_pretrain_and_train(L, T, n_random=512, n_phys=64, pre_epochs=4, epochs=1,
+                                                      sweeps=10, seed=1)
+    init, fin, x = train.kitaev_open_transfer(pre, 6, T, n_edge=2, n_phys=128, sweeps=20, epochs=4, seed=2)
+    assert init.W.shape == (5, 8, 3, 3, 3) and fin.W.shape == init.W.shape and fin.hbias.shape == (5, 8)
+    # every bank of the initial machine is the periodic CRBM
+    assert torch.equal(init.W[3], pre.W) and torch.equal(init.hbias[4], pre.hbias)
+    nlp = train.kitaev_nlp(T, boundary=1)
+    nx = nlp(x)
+    l0 = train.full_loss_nlp(x, nx, init.W, init.hbias, init.vbias)
+    l1 = train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)
+    assert np.isfinite(l1) and l1 < 1.1 * l0, (l0, l1)
+    # the edge banks moved away from the bulk bank during retraining
+    assert not torch.equal(fin.W[1], fin.W[0])
