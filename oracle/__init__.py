@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class _Params(ct.Structure):
     _fields_ = [("K", ct.c_int32), ("C", ct.c_int32), ("Lw", ct.c_int32),
                 ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p),
-                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32)]
+                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32), ("dense", ct.c_int32)]
 
 
 class _RunDesc(ct.Structure):
@@ -121,11 +121,39 @@ class CRBM:
         self.hbias = np.ascontiguousarray(hbias, dtype=np.float32).reshape(hshape)
         self.vbias = np.ascontiguousarray(vbias, dtype=np.float32).reshape(self.C)
         self._p = _Params(self.K, self.C, self.Lw, self.W.ctypes.data, self.hbias.ctypes.data,
-                          self.vbias.ctypes.data, int(self.open_cols), self.n_edge)
+                          self.vbias.ctypes.data, int(self.open_cols), self.n_edge, 0)
+        self.dense = False
 
     @property
     def p(self):
         return ct.byref(self._p)
+
+    def n_hidden(self, L: int) -> int:
+        return self.K * L * L
+
+
+class FRBM:
+    """Fully connected RBM of Sec. IV's comparison on an L x L lattice of C
+    channels: W[K][C][L][L] (hidden unit k to every visible unit), hbias[K],
+    vbias[C][L][L].  Drop-in for CRBM in the functions of this module."""
+
+    def __init__(self, W, hbias, vbias):
+        self.W = np.ascontiguousarray(W, dtype=np.float32)
+        assert self.W.ndim == 4 and self.W.shape[2] == self.W.shape[3]
+        self.K, self.C, self.Lw = self.W.shape[0], self.W.shape[1], self.W.shape[2]
+        self.hbias = np.ascontiguousarray(hbias, dtype=np.float32).reshape(self.K)
+        self.vbias = np.ascontiguousarray(vbias, dtype=np.float32).reshape(self.C, self.Lw, self.Lw)
+        self.banks, self.n_edge, self.open_cols, self.dense = 1, 0, False, True
+        self._p = _Params(self.K, self.C, self.Lw, self.W.ctypes.data, self.hbias.ctypes.data,
+                          self.vbias.ctypes.data, 0, 0, 1)
+
+    @property
+    def p(self):
+        return ct.byref(self._p)
+
+    def n_hidden(self, L: int) -> int:
+        assert L == self.Lw
+        return self.K
 
 
 # ---------------------------------------------------------------- RNG
@@ -148,13 +176,13 @@ def unit_uniform(seed: int, q: int, t: int, g: int, tag: int) -> float:
 # ---------------------------------------------------------------- CRBM pieces
 def hidden_preact(m: CRBM, v: np.ndarray, L: int) -> np.ndarray:
     v = np.ascontiguousarray(v, dtype=np.uint8).reshape(m.C, L, L)
-    a = np.zeros((m.K, L, L), np.float64)
+    a = np.zeros((m.K,) if m.dense else (m.K, L, L), np.float64)
     lib().orc_hidden_preact(m.p, _ptr(v), L, _ptr(a))
     return a
 
 
 def visible_preact(m: CRBM, h: np.ndarray, L: int) -> np.ndarray:
-    h = np.ascontiguousarray(h, dtype=np.uint8).reshape(m.K, L, L)
+    h = np.ascontiguousarray(h, dtype=np.uint8).reshape((m.K,) if m.dense else (m.K, L, L))
     b = np.zeros((m.C, L, L), np.float64)
     lib().orc_visible_preact(m.p, _ptr(h), L, _ptr(b))
     return b
@@ -172,7 +200,7 @@ def free_energy(m: CRBM, x: np.ndarray) -> np.ndarray:
 
 def gibbs_step(m: CRBM, v: np.ndarray, L: int, seed: int, t: int, g: int, substep: int = 0):
     v = np.ascontiguousarray(v, dtype=np.uint8).reshape(m.C, L, L)
-    h = np.zeros((m.K, L, L), np.uint8)
+    h = np.zeros((m.K,) if m.dense else (m.K, L, L), np.uint8)
     vo = np.zeros((m.C, L, L), np.uint8)
     scratch = np.zeros(max(m.K, m.C) * L * L, np.float64)
     ties = lib().orc_gibbs_step(m.p, L, _ptr(v), _ptr(h), _ptr(vo), seed, t, g, substep, _ptr(scratch))
@@ -186,7 +214,7 @@ def grad(m: CRBM, x: np.ndarray, gF: np.ndarray):
     g = np.ascontiguousarray(gF, dtype=np.float64).reshape(B)
     dW = np.zeros(m.W.shape, np.float64)
     dhb = np.zeros(m.hbias.shape, np.float64)
-    dvb = np.zeros(m.C, np.float64)
+    dvb = np.zeros(m.vbias.shape, np.float64)
     lib().orc_grad(m.p, _ptr(x), B, L, _ptr(g), _ptr(dW), _ptr(dhb), _ptr(dvb))
     return dW, dhb, dvb
 

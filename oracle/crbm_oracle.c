@@ -138,13 +138,20 @@ ORC_API double orc_unit_uniform(uint64_t seed, uint32_t q, uint32_t t, uint32_t 
  * L-n_edge..L-1 (right side).  With open_cols the filter window does not wrap
  * across the column edge: visible columns beyond it count as v = 0.  Rows stay
  * periodic. */
+/* dense = 1: the fully connected RBM that Sec. IV compares with (FRBM):
+ * K hidden units, each connected to all C L^2 visible units, W[K][C][L][L]
+ * with Lw = L, hbias[K], vbias[C][L][L] (one bias per visible unit). */
 typedef struct {
     int32_t K, C, Lw;
     const float* W;     /* [banks][K][C][Lw][Lw] */
     const float* hbias; /* [banks][K] */
-    const float* vbias; /* [C] */
+    const float* vbias; /* [C], or [C][L][L] when dense */
     int32_t open_cols, n_edge;
+    int32_t dense;
 } orc_params;
+
+/* number of hidden units of a configuration of side L */
+static int n_hidden(const orc_params* P, int L) { return P->dense ? P->K : P->K * L * L; }
 
 static inline int wrap(int i, int L) { int r = i % L; return r < 0 ? r + L : r; }
 
@@ -178,6 +185,16 @@ static double hbd(const orc_params* P, int bank, int k) { return (double)P->hbia
 ORC_API void orc_hidden_preact(const orc_params* P, const uint8_t* v, int L, double* a_out)
 {
     const int K = P->K, C = P->C, Lw = P->Lw;
+    if (P->dense) {
+        /* FRBM: a[k] = hb[k] + sum_q W[k][q] v[q] over all C L^2 visible units */
+        const int nv = C * L * L;
+        for (int k = 0; k < K; ++k) {
+            double s = (double)P->hbias[k];
+            for (int q = 0; q < nv; ++q) s += (double)P->W[(size_t)k * nv + q] * (double)v[q];
+            a_out[k] = s;
+        }
+        return;
+    }
     for (int k = 0; k < K; ++k)
         for (int i = 0; i < L; ++i)
             for (int j = 0; j < L; ++j) {
@@ -200,6 +217,16 @@ ORC_API void orc_hidden_preact(const orc_params* P, const uint8_t* v, int L, dou
 ORC_API void orc_visible_preact(const orc_params* P, const uint8_t* h, int L, double* b_out)
 {
     const int K = P->K, C = P->C, Lw = P->Lw;
+    if (P->dense) {
+        /* FRBM: b[q] = vb[q] + sum_k W[k][q] h[k] */
+        const int nv = C * L * L;
+        for (int q = 0; q < nv; ++q) {
+            double s = (double)P->vbias[q];
+            for (int k = 0; k < K; ++k) s += (double)P->W[(size_t)k * nv + q] * (double)h[k];
+            b_out[q] = s;
+        }
+        return;
+    }
     for (int c = 0; c < C; ++c)
         for (int x = 0; x < L; ++x)
             for (int y = 0; y < L; ++y) {
@@ -223,15 +250,19 @@ static double log2cosh(double x) { const double ax = fabs(x); return ax + log1p(
 /* CRBM free energy, Eq. (free-energy_CRBM), of one visible configuration v */
 static double free_energy_v(const orc_params* P, const uint8_t* v, int L, double* scratch)
 {
-    const int K = P->K, C = P->C, n = L * L;
+    const int C = P->C, n = L * L;
     orc_hidden_preact(P, v, L, scratch);
     double F = 0.0;
-    for (int c = 0; c < C; ++c) {
-        double nv = 0.0;
-        for (int q = 0; q < n; ++q) nv += (double)v[c * n + q];
-        F -= (double)P->vbias[c] * nv;
+    if (P->dense) {
+        for (int q = 0; q < C * n; ++q) F -= (double)P->vbias[q] * (double)v[q];
+    } else {
+        for (int c = 0; c < C; ++c) {
+            double nv = 0.0;
+            for (int q = 0; q < n; ++q) nv += (double)v[c * n + q];
+            F -= (double)P->vbias[c] * nv;
+        }
     }
-    for (int q = 0; q < K * n; ++q) F -= softplus(scratch[q]);
+    for (int q = 0; q < n_hidden(P, L); ++q) F -= softplus(scratch[q]);
     return F;
 }
 
@@ -407,10 +438,10 @@ ORC_API void orc_init_state(uint64_t seed, uint32_t g0, int n, int C, int L, int
 ORC_API int64_t orc_gibbs_step(const orc_params* P, int L, const uint8_t* v, uint8_t* h, uint8_t* vout,
                                uint64_t seed, uint32_t t, uint32_t g, uint32_t substep, double* scratch)
 {
-    const int K = P->K, C = P->C, n = L * L;
+    const int C = P->C, n = L * L;
     int64_t ties = 0;
     orc_hidden_preact(P, v, L, scratch);
-    for (int q = 0; q < K * n; ++q) {
+    for (int q = 0; q < n_hidden(P, L); ++q) {
         const double u = orc_unit_uniform(seed, (uint32_t)q, t, g, ST_HID | (substep << 8));
         const double p = sigmoid(scratch[q]);
         if (fabs(u - p) < 1e-12) ++ties;
@@ -659,11 +690,35 @@ ORC_API void orc_tempering_swap(const orc_run_desc* D, int C, const double* T, i
 /* dF/dvb[c]         = -sum_ij v[c][i][j]                                */
 /* out = sum_n g_n dF(x_n)/dtheta; with several banks, hidden column j    */
 /* contributes to the bank that owns it; dW, dhb have the banks' layout.  */
+/* FRBM (dense): dF/dW[k][q] = -sigma(a[k]) v[q], dF/dhb[k] = -sigma(a[k]),*/
+/* dF/dvb[q] = -v[q].                                                     */
 /* ------------------------------------------------------------------ */
 ORC_API void orc_grad(const orc_params* P, const int8_t* x, int B, int L, const double* gF,
                       double* dW, double* dhb, double* dvb)
 {
     const int K = P->K, C = P->C, Lw = P->Lw, n = L * L;
+    if (P->dense) {
+        const int nv = C * n;
+        memset(dW, 0, sizeof(double) * (size_t)K * nv);
+        memset(dhb, 0, sizeof(double) * (size_t)K);
+        memset(dvb, 0, sizeof(double) * (size_t)nv);
+        uint8_t* v = (uint8_t*)malloc((size_t)nv);
+        double* a = (double*)malloc(sizeof(double) * (size_t)K);
+        for (int bi = 0; bi < B; ++bi) {
+            const double g = gF[bi];
+            spins_to_visible(x + (size_t)bi * nv, C, L, v);
+            orc_hidden_preact(P, v, L, a);
+            for (int k = 0; k < K; ++k) {
+                const double sg = sigmoid(a[k]);
+                dhb[k] -= g * sg;
+                for (int q = 0; q < nv; ++q) dW[(size_t)k * nv + q] -= g * sg * (double)v[q];
+            }
+            for (int q = 0; q < nv; ++q) dvb[q] -= g * (double)v[q];
+        }
+        free(v);
+        free(a);
+        return;
+    }
     const int nb = 1 + 2 * (P->n_edge > 0 ? P->n_edge : 0);
     const int nW = K * C * Lw * Lw;
     memset(dW, 0, sizeof(double) * (size_t)nb * nW);

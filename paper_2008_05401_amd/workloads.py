@@ -156,3 +156,13 @@ def lcrbm_from_crbm(f: Filters, n_edge: int, edge_std: float = 0.0, seed: int = 
         W[1:] += rng.normal(0.0, edge_std, W[1:].shape).astype(np.float32)
         hb[1:] += rng.normal(0.0, edge_std, hb[1:].shape).astype(np.float32)
     return Filters(W, hb, f.vbias.copy())
+
+
+def random_frbm(K: int, C: int, L: int, std: float, bias_std: float = 0.0, seed: int = 0) -> Filters:
+    """A fully connected RBM on an L x L lattice of C channels: W[K][C][L][L]
+    ~ N(0, std), hbias[K] and vbias[C][L][L] ~ N(0, bias_std)."""
+    rng = np.random.default_rng(seed)
+    W = rng.normal(0.0, std, (K, C, L, L)).astype(np.float32)
+    hb = rng.normal(0.0, bias_std, K).astype(np.float32) if bias_std > 0 else np.zeros(K, np.float32)
+    vb = rng.normal(0.0, bias_std, (C, L, L)).astype(np.float32) if bias_std > 0 else np.zeros((C, L, L), np.float32)
+    return Filters(W, hb, vb)
