@@ -171,6 +171,29 @@ def kitaev(sweeps6=20, sweeps12=2):
     return out
 
 
+def frbm(L=8, n=256, sweeps=10):
+    """Sec. IV's comparison of proposals on the Kitaev eta model (C=1, L=8,
+    256 chains, T log-uniform in [0.005, 0.05]): ms per sweep with the CRBM
+    (K=8, 3x3 ~ N(0, 0.1)) and with fully connected RBMs of 64 and 128
+    hidden units (W ~ N(0, 0.05)); the dense Gibbs passes run per chain from
+    LDS inside the fused sweep."""
+    from paper_2008_05401_amd import api, workloads as WL
+    T = WL.kitaev_temperatures(n)
+    cases = (("crbm_K8_3x3", api.CRBMParams.from_filters(WL.random_filters(8, 1, 3, 0.1, seed=0))),
+             ("frbm_64_hidden", api.CRBMParams.from_filters(WL.random_frbm(64, 1, L, 0.05, seed=0), dense=True)),
+             ("frbm_128_hidden", api.CRBMParams.from_filters(WL.random_frbm(128, 1, L, 0.05, seed=0), dense=True)))
+    out = {}
+    for name, p in cases:
+        job = api.Job(p, api.KITAEV, L, T, seed=0)
+        job.run(1)
+        ms = _timed(lambda: job.run(sweeps)) / sweeps
+        st = job.stats()
+        out[name] = {"ms_per_sweep": ms, "mh_steps_per_s": n / (ms * 1e-3),
+                     "acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
+        job.close()
+    return out
+
+
 def tempering(blocks=20, block_sweeps=5):
     """Parallel tempering with the exchange correction (App. B): the batched
     Ising config (4096 chains, L=64, K=8 5x5 ~ N(0,0.05), 32 rungs
@@ -489,6 +512,7 @@ def main():
     if not args.no_extra:
         out["kitaev"] = kitaev()
         out["autocorrelation"] = autocorrelation_times()
+        out["frbm"] = frbm()
         out["tempering"] = tempering()
         out["training"] = training_and_transfer()
         out["kitaev_training"] = kitaev_training_and_transfer()

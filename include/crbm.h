@@ -92,6 +92,12 @@ typedef struct {
     const float* vbias; /* device [C] */
     int32_t open_cols;  /* 0: windows wrap in both directions; 1: open columns */
     int32_t n_edge;     /* unshared banks per side */
+    int32_t dense;      /* 1: the fully connected RBM (FRBM) of the Sec. IV
+                           comparison instead of a convolution: K in [1, 256]
+                           hidden units each connected to all C L^2 visible
+                           units, Lw = L, W [K][C][L][L], hbias [K], vbias
+                           [C][L][L] (one bias per visible unit); open_cols =
+                           n_edge = 0 */
 } crbm_params;
 
 /* One job: n_chains chains on an L x L lattice.

@@ -24,7 +24,7 @@ class CRBMError(RuntimeError):
 class crbm_params(ct.Structure):
     _fields_ = [("K", ct.c_int32), ("C", ct.c_int32), ("Lw", ct.c_int32),
                 ("W", ct.c_void_p), ("hbias", ct.c_void_p), ("vbias", ct.c_void_p),
-                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32)]
+                ("open_cols", ct.c_int32), ("n_edge", ct.c_int32), ("dense", ct.c_int32)]
 
 
 class crbm_batch_desc(ct.Structure):

@@ -42,13 +42,19 @@ class CRBMParams:
     hbias[1+2n][K] (bank 0 for the bulk hidden columns, banks 1..n for the
     left columns 0..n-1, banks n+1..2n for the right columns L-n..L-1);
     open_cols (default: on when there are edge banks) stops the filter windows
-    at the column edge."""
+    at the column edge.
 
-    def __init__(self, W, hbias, vbias, device=None, open_cols=None):
+    dense=True makes it the fully connected RBM of the Sec. IV comparison:
+    W[K][C][L][L] connects hidden unit k to every visible unit of an L x L
+    lattice, hbias[K], vbias[C][L][L]."""
+
+    def __init__(self, W, hbias, vbias, device=None, open_cols=None, dense: bool = False):
         dev = _dev(device)
         self.W = torch.as_tensor(np.asarray(W, np.float32) if not torch.is_tensor(W) else W,
                                  dtype=torch.float32, device=dev).contiguous()
         assert self.W.dim() in (4, 5) and self.W.shape[-1] == self.W.shape[-2]
+        self.dense = bool(dense)
+        assert not (self.dense and self.W.dim() != 4)
         self.banks = 1 if self.W.dim() == 4 else int(self.W.shape[0])
         assert self.banks % 2 == 1
         self.n_edge = (self.banks - 1) // 2
@@ -58,16 +64,17 @@ class CRBMParams:
         self.hbias = torch.as_tensor(np.asarray(hbias, np.float32) if not torch.is_tensor(hbias) else hbias,
                                      dtype=torch.float32, device=dev).contiguous().reshape(hshape)
         self.vbias = torch.as_tensor(np.asarray(vbias, np.float32) if not torch.is_tensor(vbias) else vbias,
-                                     dtype=torch.float32, device=dev).contiguous().reshape(-1)
-        assert self.vbias.numel() == self.C
+                                     dtype=torch.float32, device=dev).contiguous()
+        self.vbias = self.vbias.reshape((self.C, self.Lw, self.Lw) if self.dense else (-1,))
+        assert self.vbias.numel() == (self.C * self.Lw * self.Lw if self.dense else self.C)
 
     @classmethod
-    def from_filters(cls, f, device=None, open_cols=None):
-        return cls(f.W, f.hbias, f.vbias, device, open_cols)
+    def from_filters(cls, f, device=None, open_cols=None, dense: bool = False):
+        return cls(f.W, f.hbias, f.vbias, device, open_cols, dense)
 
     def struct(self) -> C.crbm_params:
         return C.crbm_params(self.K, self.C, self.Lw, self.W.data_ptr(), self.hbias.data_ptr(),
-                             self.vbias.data_ptr(), int(self.open_cols), self.n_edge)
+                             self.vbias.data_ptr(), int(self.open_cols), self.n_edge, int(self.dense))
 
 
 class Job:
@@ -258,19 +265,20 @@ class CRBMFreeEnergy(torch.autograd.Function):
     (None, dW, dhbias, dvbias) with d = sum_b grad_out[b] dF_b/dtheta."""
 
     @staticmethod
-    def forward(ctx, x, W, hbias, vbias, open_cols=None):
-        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=open_cols)
+    def forward(ctx, x, W, hbias, vbias, open_cols=None, dense=False):
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=open_cols, dense=dense)
         ctx.save_for_backward(x, W, hbias, vbias)
-        ctx.open_cols = open_cols
+        ctx.open_cols, ctx.dense = open_cols, dense
         return free_energy(p, x)
 
     @staticmethod
     def backward(ctx, gout):
         x, W, hbias, vbias = ctx.saved_tensors
-        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=ctx.open_cols)
+        p = CRBMParams(W.detach(), hbias.detach(), vbias.detach(), device=W.device, open_cols=ctx.open_cols,
+                       dense=ctx.dense)
         dW, dhb, dvb = grad(p, x, gout.to(torch.float32))
-        return None, dW, dhb.reshape(hbias.shape), dvb, None
+        return None, dW, dhb.reshape(hbias.shape), dvb.reshape(vbias.shape), None, None
 
 
-def crbm_free_energy_fn(x, W, hbias, vbias, open_cols=None):
-    return CRBMFreeEnergy.apply(x, W, hbias, vbias, open_cols)
+def crbm_free_energy_fn(x, W, hbias, vbias, open_cols=None, dense=False):
+    return CRBMFreeEnergy.apply(x, W, hbias, vbias, open_cols, dense)

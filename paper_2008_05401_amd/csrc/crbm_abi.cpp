@@ -46,7 +46,11 @@ static_assert(sizeof(crbm_chain_stats) == sizeof(ChainRec), "record layout");
 crbm_status check_params(const crbm_params* p)
 {
     if (!p) return fail(CRBM_EINVAL, "params is NULL");
-    if (p->K < 1 || p->K > 64) return fail(CRBM_EINVAL, "K=%d outside [1,64]", p->K);
+    if (p->dense != 0 && p->dense != 1) return fail(CRBM_EINVAL, "dense=%d must be 0 or 1", p->dense);
+    const int kmax = p->dense ? 256 : 64;
+    if (p->K < 1 || p->K > kmax) return fail(CRBM_EINVAL, "K=%d outside [1,%d]", p->K, kmax);
+    if (p->dense && (p->open_cols != 0 || p->n_edge != 0))
+        return fail(CRBM_EINVAL, "a dense RBM takes no open_cols or filter banks");
     if (p->C != 1 && p->C != 3) return fail(CRBM_EINVAL, "C=%d must be 1 or 3", p->C);
     if (p->Lw < 1 || p->Lw > 8) return fail(CRBM_EINVAL, "Lw=%d outside [1,8]", p->Lw);
     if (!p->W || !p->hbias || !p->vbias) return fail(CRBM_EINVAL, "W, hbias and vbias must be device pointers");
@@ -62,6 +66,7 @@ crbm_status check_lattice(const crbm_params* p, int L)
     if (L < 1 || L > 256) return fail(CRBM_EINVAL, "L=%d outside [1,256]", L);
     if (p->Lw > L) return fail(CRBM_EINVAL, "Lw=%d larger than L=%d", p->Lw, L);
     if (2 * p->n_edge > L) return fail(CRBM_EINVAL, "2*n_edge=%d larger than L=%d", 2 * p->n_edge, L);
+    if (p->dense && p->Lw != L) return fail(CRBM_EINVAL, "a dense RBM built for L=%d used at L=%d", p->Lw, L);
     return CRBM_OK;
 }
 
@@ -111,7 +116,7 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->target == CRBM_GIBBS && d->rbm_state)
         return fail(CRBM_EINVAL, "a persistent CRBM replica needs a physical target (got CRBM_GIBBS)");
     Plan pl{};
-    const bool plain = p->open_cols == 0 && p->n_edge == 0 && d->boundary == 0;
+    const bool plain = p->open_cols == 0 && p->n_edge == 0 && p->dense == 0 && d->boundary == 0;
     if (plain && d->target != CRBM_KITAEV && p->C == 1 && ising_fast_supported(p->K, p->Lw, d->L)) {
         pl.kernel = K_ISING_FAST;
         pl.nt = ising_fast_threads(d->L);
@@ -123,7 +128,7 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
         pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
         // the Kitaev eigen-step is latency-bound: one 16-wave workgroup per chain from N = 16 on
         if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = 1024;
-        pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target, banks_of(p));
+        pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target, banks_of(p), p->dense);
     }
     if (pl.lds > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "job needs %zu bytes of LDS per chain (limit %zu)", pl.lds, kLdsLimit);
@@ -267,6 +272,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.open_cols = params->open_cols;
     j.n_edge = params->n_edge;
     j.boundary = desc->boundary;
+    j.dense = params->dense;
     hipError_t e = hipMemcpyAsync(c->job_dev, &c->job, sizeof(JobDev), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -279,7 +285,8 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     P.block_begin[1] = desc->n_chains;
     P.n_jobs = 1;
     P.mode = MODE_INIT;
-    const size_t lds = init_lds(params->K, params->C, params->Lw, desc->L, desc->target, banks_of(params));
+    const size_t lds = init_lds(params->K, params->C, params->Lw, desc->L, desc->target, banks_of(params),
+                                params->dense);
     if (lds > kLdsLimit) {
         delete c;
         return fail(CRBM_EUNSUPPORTED, "initialisation needs %zu bytes of LDS", lds);
@@ -396,6 +403,11 @@ crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x, int32_t
     if (st != CRBM_OK) return st;
     if (B == 0) return CRBM_OK;
     if (!x || !F_out) return fail(CRBM_EINVAL, "x and F_out must be device pointers");
+    if (params->dense) {
+        hipError_t e = launch_free_energy_dense(params->W, params->hbias, params->vbias, params->K, params->C * L * L,
+                                                x, B, F_out, (hipStream_t)stream);
+        return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_free_energy launch");
+    }
     if (free_energy_lds(params->K, params->C, params->Lw, L, banks_of(params)) > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "free energy needs too much LDS for L=%d", L);
     hipError_t e = launch_free_energy(params->W, params->hbias, params->vbias, params->K, params->C, params->Lw,
@@ -431,6 +443,10 @@ crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C,
 size_t crbm_grad_workspace_size(const crbm_params* params, int32_t B)
 {
     if (check_params(params) != CRBM_OK || B < 0) return 0;
+    if (params->dense) {
+        const size_t nv = (size_t)params->C * params->Lw * params->Lw;
+        return round_up(std::max<size_t>(1, (size_t)B) * (params->K * nv + params->K + nv) * sizeof(double), 256);
+    }
     const size_t P = (size_t)banks_of(params) * ((size_t)params->K * params->C * params->Lw * params->Lw + params->K) +
                      params->C;
     return round_up(std::max<size_t>(1, (size_t)B) * P * sizeof(double), 256);
@@ -449,6 +465,13 @@ crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int
     const size_t need = crbm_grad_workspace_size(params, B);
     if (!workspace || workspace_bytes < need)
         return fail(CRBM_EBUDGET, "grad workspace of %zu bytes, %zu needed", workspace_bytes, need);
+    if (params->dense) {
+        if (grad_dense_lds(params->K, params->C * L * L) > kLdsLimit)
+            return fail(CRBM_EUNSUPPORTED, "gradient needs too much LDS for L=%d", L);
+        hipError_t e = launch_grad_dense(params->W, params->hbias, params->K, params->C * L * L, x, B, gF,
+                                         (double*)workspace, dW, dhbias, dvbias, (hipStream_t)stream);
+        return e == hipSuccess ? CRBM_OK : hip_fail(e, "crbm_grad launch");
+    }
     if (grad_lds(params->K, params->C, params->Lw, L, banks_of(params)) > kLdsLimit)
         return fail(CRBM_EUNSUPPORTED, "gradient needs too much LDS for L=%d", L);
     hipError_t e = launch_grad(params->W, params->hbias, params->K, params->C, params->Lw, params->open_cols,

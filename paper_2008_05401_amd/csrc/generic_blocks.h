@@ -8,13 +8,18 @@
 // by the bulk, banks 1..ne owned by the hidden columns 0..ne-1 and banks
 // ne+1..2ne by the columns L-ne..L-1; with `open` the window stops at the
 // column edge (columns past it count as v = 0) while rows stay periodic.
+//
+// With `dense` the layer is the fully connected RBM of the Sec. IV
+// comparison: K hidden units, each connected to all nv = C L^2 visible units,
+// W[K][nv] held in LDS with row stride nv + 1 (so that the lanes of a wave,
+// one hidden unit each, hit distinct banks), hbias[K], vbias[nv].
 #pragma once
 #include "device_common.h"
 
 namespace crbm {
 
 struct ConvGeo {
-    int K, C, LW, L, open, ne;
+    int K, C, LW, L, open, ne, dense;
     // filter bank of hidden column j
     __device__ __forceinline__ int bank(int j) const
     {
@@ -123,12 +128,51 @@ __device__ __forceinline__ float preact_visible_f(const float* Ws, const float* 
     return acc;
 }
 
+// ---- fully connected layer (W in LDS with row stride nv + 1)
+__device__ __forceinline__ float dense_hidden_f(const float* Ws, const float* hbs, const uint8_t* v, int nv, int k)
+{
+    const float* w = Ws + (size_t)k * (nv + 1);
+    float acc = hbs[k];
+    for (int q = 0; q < nv; ++q) acc = fmaf(w[q], (float)v[q], acc);
+    return acc;
+}
+
+__device__ __forceinline__ double dense_hidden_d(const float* Ws, const float* hbs, const uint8_t* v, int nv, int k)
+{
+    const float* w = Ws + (size_t)k * (nv + 1);
+    double acc = (double)hbs[k];
+    for (int q = 0; q < nv; ++q) acc += (double)w[q] * (double)v[q];
+    return acc;
+}
+
+__device__ __forceinline__ float dense_visible_f(const float* Ws, const float* vbs, const uint8_t* h, int K, int nv,
+                                                 int q)
+{
+    float acc = vbs[q];
+    for (int k = 0; k < K; ++k) acc = fmaf(Ws[(size_t)k * (nv + 1) + q], (float)h[k], acc);
+    return acc;
+}
+
+__device__ __forceinline__ double dense_visible_d(const float* Ws, const float* vbs, const uint8_t* h, int K, int nv,
+                                                  int q)
+{
+    double acc = (double)vbs[q];
+    for (int k = 0; k < K; ++k) acc += (double)Ws[(size_t)k * (nv + 1) + q] * (double)h[k];
+    return acc;
+}
+
 // F(v) in FP64 over the workgroup (all threads receive it)
 __device__ inline double free_energy_block(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v,
                                            const ConvGeo& G, double* red)
 {
     const int L = G.L, LL = L * L;
     double fl = 0.0;
+    if (G.dense) {
+        const int nv = G.C * LL;
+        for (int k = threadIdx.x; k < G.K; k += blockDim.x) fl -= softplus_d(dense_hidden_d(Ws, hbs, v, nv, k));
+        for (int q = threadIdx.x; q < nv; q += blockDim.x) fl -= (double)vbs[q] * (double)v[q];
+        return block_sum(fl, red);
+    }
     for (int q = threadIdx.x; q < G.K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
         fl -= softplus_d(preact_hidden_d(Ws, hbs, v, G, k, i, j));

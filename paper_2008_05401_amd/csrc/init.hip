@@ -9,10 +9,11 @@
 
 namespace crbm {
 
-__host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, int target, int banks)
+__host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense)
 {
+    const size_t nv = (size_t)C * L * L;
     size_t o = 64 * 8;
-    o += ((size_t)banks * (K * C * LW * LW + K) + C) * 4;
+    o += dense ? ((size_t)K * (nv + 1) + K + nv) * 4 : ((size_t)banks * (K * C * LW * LW + K) + C) * 4;
     o = (o + 15) / 16 * 16;
     o += (size_t)C * L * L;
     o = (o + 15) / 16 * 16;
@@ -29,23 +30,29 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     const int g = (int)blockIdx.x - P.block_begin[jb];
     if (g >= J.n_chains) return;
     const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L;
-    const int nb = 1 + 2 * J.n_edge, nW = nb * K * C * LW * LW;
-    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge};
+    const int nb = 1 + 2 * J.n_edge, nvis = C * LL;
+    const int nW = J.dense ? K * (nvis + 1) : nb * K * C * LW * LW;  // LDS floats of W
+    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge, J.dense};
     const int tid = threadIdx.x, NT = blockDim.x;
     double* red = (double*)smem;
     float* Ws = (float*)(smem + 64 * 8);
     float* hbs = Ws + nW;
     float* vbs = hbs + nb * K;
-    size_t o = 64 * 8 + ((size_t)nW + nb * K + C) * 4;
+    const int nvb = J.dense ? nvis : C;
+    size_t o = 64 * 8 + ((size_t)nW + nb * K + nvb) * 4;
     o = (o + 15) / 16 * 16;
     uint8_t* v = smem + o;
     o += (size_t)C * LL;
     o = (o + 15) / 16 * 16;
     double* kit = (double*)(smem + o);
 
-    for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
+    if (J.dense) {
+        for (int q = tid; q < K * nvis; q += NT) Ws[(q / nvis) * (nvis + 1) + q % nvis] = J.W[q];
+    } else {
+        for (int q = tid; q < nW; q += NT) Ws[q] = J.W[q];
+    }
     for (int q = tid; q < nb * K; q += NT) hbs[q] = J.hb[q];
-    for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
+    for (int q = tid; q < nvb; q += NT) vbs[q] = J.vb[q];
     const uint32_t gid = J.chain_offset + (uint32_t)g;
     const uint32_t k0 = (uint32_t)J.seed, k1 = (uint32_t)(J.seed >> 32);
     int8_t* state = J.state + (size_t)g * C * LL;
@@ -89,9 +96,9 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
     }
 }
 
-size_t init_lds(int K, int C, int LW, int L, int target, int banks)
+size_t init_lds(int K, int C, int LW, int L, int target, int banks, int dense)
 {
-    return init_lds_bytes(K, C, LW, L, target, banks);
+    return init_lds_bytes(K, C, LW, L, target, banks, dense);
 }
 
 hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s)

@@ -16,6 +16,13 @@ size_t kitaev_weight_lds(int C, int L);
 hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_cols, double Jx, double Jy, double Jz,
                                 const double* T, double* S, hipStream_t s);
 size_t grad_lds(int K, int C, int LW, int L, int banks);
+// fully connected RBM: W[K][nv], hbias[K], vbias[nv], nv = C L^2
+size_t free_energy_dense_lds(int nv);
+hipError_t launch_free_energy_dense(const float* W, const float* hb, const float* vb, int K, int nv, const int8_t* x,
+                                    int B, double* F, hipStream_t s);
+size_t grad_dense_lds(int K, int nv);
+hipError_t launch_grad_dense(const float* W, const float* hb, int K, int nv, const int8_t* x, int B, const float* gF,
+                             double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
 hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, int open, int ne, const int8_t* x, int B,
                        int L, const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
 

@@ -61,6 +61,41 @@ __global__ __launch_bounds__(256) void free_energy_kernel(const float* __restric
     if (threadIdx.x == 0) F[blockIdx.x] = tot;
 }
 
+// F of the fully connected RBM (Sec. IV comparison): W[K][nv], hbias[K],
+// vbias[nv], nv = C L^2; FP64 terms and sums, one workgroup per state.
+__global__ __launch_bounds__(256) void free_energy_dense_kernel(const float* __restrict__ W,
+                                                                const float* __restrict__ hb,
+                                                                const float* __restrict__ vb, int K, int nv,
+                                                                const int8_t* __restrict__ x, double* __restrict__ F)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* red = (double*)smem;
+    uint8_t* v = (uint8_t*)(red + 64);
+    const int8_t* xs = x + (size_t)blockIdx.x * nv;
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) v[q] = xs[q] > 0;
+    __syncthreads();
+    double fl = 0.0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const float* w = W + (size_t)k * nv;
+        double acc = (double)hb[k];
+        for (int q = 0; q < nv; ++q) acc += v[q] ? (double)w[q] : 0.0;
+        fl -= softplus_d(acc);
+    }
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) fl -= (double)vb[q] * (double)v[q];
+    const double tot = block_sum(fl, red);
+    if (threadIdx.x == 0) F[blockIdx.x] = tot;
+}
+
+size_t free_energy_dense_lds(int nv) { return 64 * 8 + (size_t)nv + 16; }
+
+hipError_t launch_free_energy_dense(const float* W, const float* hb, const float* vb, int K, int nv, const int8_t* x,
+                                    int B, double* F, hipStream_t s)
+{
+    hipLaunchKernelGGL(free_energy_dense_kernel, dim3(B), dim3(256), free_energy_dense_lds(nv), s, W, hb, vb, K, nv, x,
+                       F);
+    return hipGetLastError();
+}
+
 size_t free_energy_lds(int K, int C, int LW, int L, int banks)
 {
     return 64 * 8 + (size_t)banks * (K * C * LW * LW + K) * 8 + (size_t)C * L * L + 16;
@@ -222,6 +257,53 @@ __global__ __launch_bounds__(256) void grad_stage2(const double* __restrict__ pa
     if (p < nW) dW[p] = (float)s;
     else if (p < nW + K) dhb[p - nW] = (float)s;
     else dvb[p - nW - K] = (float)s;
+}
+
+// Backward of the fully connected RBM's F: parameters W[K][nv], hbias[K],
+// vbias[nv]; dF/dW[k][q] = -sigma(a_k) v_q, dF/dhb[k] = -sigma(a_k),
+// dF/dvb[q] = -v_q.  Stage 1 per sample as above, stage 2 shared.
+__global__ __launch_bounds__(256) void grad_dense_stage1(const float* __restrict__ W, const float* __restrict__ hb,
+                                                         int K, int nv, const int8_t* __restrict__ x,
+                                                         const float* __restrict__ gF, double* __restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int P = K * nv + K + nv;
+    float* sg = (float*)smem;
+    uint8_t* v = (uint8_t*)(sg + K);
+    const int8_t* xs = x + (size_t)blockIdx.x * nv;
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) v[q] = xs[q] > 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const float* w = W + (size_t)k * nv;
+        float acc = hb[k];
+        for (int q = 0; q < nv; ++q) acc = fmaf(w[q], (float)v[q], acc);
+        sg[k] = (float)(1.0 / (1.0 + exp(-(double)acc)));
+    }
+    __syncthreads();
+    const double gb = (double)gF[blockIdx.x];
+    double* out = part + (size_t)blockIdx.x * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        double s;
+        if (p < K * nv) s = v[p % nv] ? (double)sg[p / nv] : 0.0;
+        else if (p < K * nv + K) s = (double)sg[p - K * nv];
+        else s = (double)v[p - K * nv - K];
+        out[p] = -gb * s;
+    }
+}
+
+size_t grad_dense_lds(int K, int nv) { return (size_t)K * 4 + (size_t)nv + 16; }
+
+hipError_t launch_grad_dense(const float* W, const float* hb, int K, int nv, const int8_t* x, int B, const float* gF,
+                             double* part, float* dW, float* dhb, float* dvb, hipStream_t s)
+{
+    const int P = K * nv + K + nv;
+    if (B > 0) {
+        hipLaunchKernelGGL(grad_dense_stage1, dim3(B), dim3(256), grad_dense_lds(K, nv), s, W, hb, K, nv, x, gF, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(grad_stage2, dim3((P + 255) / 256), dim3(256), 0, s, part, B, P, K * nv, K, dW, dhb, dvb);
+    return hipGetLastError();
 }
 
 size_t grad_lds(int K, int C, int LW, int L, int banks)

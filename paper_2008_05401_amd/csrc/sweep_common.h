@@ -28,6 +28,7 @@ struct JobDev {
     int open_cols;  // CRBM windows stop at the column edge (locally connected CRBM)
     int n_edge;     // unshared filter banks per side; banks = 1 + 2 n_edge
     int boundary;   // target lattice: 0 periodic, 1 open columns
+    int dense;      // fully connected RBM: W[K][C L^2], hbias[K], vbias[C L^2]
 };
 
 constexpr int MAX_JOBS_PER_LAUNCH = 128;
@@ -44,12 +45,12 @@ struct SweepLaunch {
     int pad;
 };
 
-size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks);
+size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense);
 hipError_t launch_autocorr(const double* trace, int n, int len, int start, int max_lag, double c_win, double* out,
                            double* tau, int* window, hipStream_t s);
 hipError_t launch_tempering_swap(const JobDev* job_dev, int n_pairs, int n_ladders, int q0, uint32_t round,
                                  int target, hipStream_t s);
-size_t init_lds(int K, int C, int LW, int L, int target, int banks);
+size_t init_lds(int K, int C, int LW, int L, int target, int banks, int dense);
 hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s);
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);
 

@@ -26,28 +26,29 @@ struct GenericLds {
     int off_red, off_W, off_hb, off_vb, off_dah, off_dav, off_v, off_h, off_kit, total;
 };
 
-__host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, int L, int target, int banks)
+__host__ __device__ inline GenericLds generic_lds_layout(int K, int C, int LW, int L, int target, int banks,
+                                                        int dense)
 {
     GenericLds g;
-    const int LL = L * L;
+    const int LL = L * L, nv = C * LL;
     int o = 0;
     auto al = [](int x, int a) { return (x + a - 1) / a * a; };
     g.off_red = o;
     o += 64 * 8;
     g.off_W = o;
-    o += al(banks * K * C * LW * LW * 4, 16);
+    o += al(dense ? K * (nv + 1) * 4 : banks * K * C * LW * LW * 4, 16);
     g.off_hb = o;
     o += al(banks * K * 4, 16);
     g.off_vb = o;
-    o += al(C * 4, 16);
+    o += al((dense ? nv : C) * 4, 16);
     g.off_dah = o;
     o += al(banks * K * 4, 16);
     g.off_dav = o;
-    o += al(C * 4, 16);
+    o += al((dense ? nv : C) * 4, 16);
     g.off_v = o;
     o += al(3 * C * LL, 16);
     g.off_h = o;
-    o += al(K * LL, 16);
+    o += al(dense ? K : K * LL, 16);
     g.off_kit = o;
     if (target == 1) o += (int)kitaev_lds_bytes(L);
     g.total = al(o, 16);
@@ -66,9 +67,10 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 
     const int K = J.K, C = J.C, LW = J.LW, L = J.L, LL = L * L;
     const int nb = 1 + 2 * J.n_edge;
-    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge};
+    const ConvGeo G{K, C, LW, L, J.open_cols, J.n_edge, J.dense};
     const int tid = threadIdx.x;
-    const GenericLds lay = generic_lds_layout(K, C, LW, L, J.target, nb);
+    const int nvis = C * LL;  // visible units
+    const GenericLds lay = generic_lds_layout(K, C, LW, L, J.target, nb, J.dense);
     double* red = (double*)(smem + lay.off_red);
     long long* redi = (long long*)(smem + lay.off_red);
     float* Ws = (float*)(smem + lay.off_W);
@@ -81,27 +83,45 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
     double* kit = (double*)(smem + lay.off_kit);
 
     const int nW = K * C * LW * LW;
-    for (int q = tid; q < nb * nW; q += NT) Ws[q] = J.W[q];
-    for (int q = tid; q < nb * K; q += NT) hbs[q] = J.hb[q];
-    for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
-    __syncthreads();
-    // error bounds of the float32 pre-activations (recursive fma summation):
-    // per bank and hidden channel; a visible unit sums terms of several banks,
-    // so its bound takes the largest |W| over the banks term by term
-    for (int bk = tid; bk < nb * K; bk += NT) {
-        float s = fabsf(hbs[bk]);
-        for (int q = 0; q < C * LW * LW; ++q) s += fabsf(Ws[bk * C * LW * LW + q]);
-        dAh[bk] = gamma_f32(C * LW * LW + 2) * s * 1.001f;
-    }
-    for (int c = tid; c < C; c += NT) {
-        float s = fabsf(vbs[c]);
-        for (int k = 0; k < K; ++k)
-            for (int q = 0; q < LW * LW; ++q) {
-                float m = 0.0f;
-                for (int b = 0; b < nb; ++b) m = fmaxf(m, fabsf(Ws[b * nW + (k * C + c) * LW * LW + q]));
-                s += m;
-            }
-        dAv[c] = gamma_f32(K * LW * LW + 2) * s * 1.001f;
+    if (G.dense) {
+        for (int q = tid; q < K * nvis; q += NT) Ws[(q / nvis) * (nvis + 1) + q % nvis] = J.W[q];
+        for (int q = tid; q < K; q += NT) hbs[q] = J.hb[q];
+        for (int q = tid; q < nvis; q += NT) vbs[q] = J.vb[q];
+        __syncthreads();
+        // error bounds: hidden unit k sums nv terms, visible unit q sums K terms
+        for (int k = tid; k < K; k += NT) {
+            float s = fabsf(hbs[k]);
+            for (int q = 0; q < nvis; ++q) s += fabsf(Ws[k * (nvis + 1) + q]);
+            dAh[k] = gamma_f32(nvis + 2) * s * 1.001f;
+        }
+        for (int q = tid; q < nvis; q += NT) {
+            float s = fabsf(vbs[q]);
+            for (int k = 0; k < K; ++k) s += fabsf(Ws[k * (nvis + 1) + q]);
+            dAv[q] = gamma_f32(K + 2) * s * 1.001f;
+        }
+    } else {
+        for (int q = tid; q < nb * nW; q += NT) Ws[q] = J.W[q];
+        for (int q = tid; q < nb * K; q += NT) hbs[q] = J.hb[q];
+        for (int q = tid; q < C; q += NT) vbs[q] = J.vb[q];
+        __syncthreads();
+        // error bounds of the float32 pre-activations (recursive fma summation):
+        // per bank and hidden channel; a visible unit sums terms of several banks,
+        // so its bound takes the largest |W| over the banks term by term
+        for (int bk = tid; bk < nb * K; bk += NT) {
+            float s = fabsf(hbs[bk]);
+            for (int q = 0; q < C * LW * LW; ++q) s += fabsf(Ws[bk * C * LW * LW + q]);
+            dAh[bk] = gamma_f32(C * LW * LW + 2) * s * 1.001f;
+        }
+        for (int c = tid; c < C; c += NT) {
+            float s = fabsf(vbs[c]);
+            for (int k = 0; k < K; ++k)
+                for (int q = 0; q < LW * LW; ++q) {
+                    float m = 0.0f;
+                    for (int b = 0; b < nb; ++b) m = fmaxf(m, fabsf(Ws[b * nW + (k * C + c) * LW * LW + q]));
+                    s += m;
+                }
+            dAv[c] = gamma_f32(K * LW * LW + 2) * s * 1.001f;
+        }
     }
 
     const uint32_t gid = J.chain_offset + (uint32_t)g;
@@ -152,13 +172,22 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             const uint8_t* vs = vb3 + src * C * LL;
             uint8_t* vd = vb3 + dst * C * LL;
             // hidden pass
-            const int nh = K * LL, ngh = (nh + 3) >> 2;
+            const int nh = G.dense ? K : K * LL, ngh = (nh + 3) >> 2;
             for (int gi = tid; gi < ngh; gi += NT) {
                 const u32x4 r = philox10((uint32_t)gi, t, gid, STREAM_HID | ((uint32_t)sub << 8), k0, k1);
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const int q = 4 * gi + w;
-                    if (q < nh) {
+                    if (q < nh && G.dense) {
+                        const float a = dense_hidden_f(Ws, hbs, vs, nvis, q);
+                        bool near;
+                        bool on = bernoulli_fast(a, word_of(r, w), dAh[q], near);
+                        if (near) {
+                            on = bernoulli_exact(dense_hidden_d(Ws, hbs, vs, nvis, q), word_of(r, w));
+                            ++nre;
+                        }
+                        h[q] = on;
+                    } else if (q < nh) {
                         const int k = q / LL, rr = q - k * LL, i = rr / L, j = rr - i * L;
                         const float a = preact_hidden_f(Ws, hbs, vs, G, k, i, j);
                         bool near;
@@ -179,7 +208,16 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
                     const int q = 4 * gi + w;
-                    if (q < nv) {
+                    if (q < nv && G.dense) {
+                        const float b = dense_visible_f(Ws, vbs, h, K, nvis, q);
+                        bool near;
+                        bool on = bernoulli_fast(b, word_of(r, w), dAv[q], near);
+                        if (near) {
+                            on = bernoulli_exact(dense_visible_d(Ws, vbs, h, K, nvis, q), word_of(r, w));
+                            ++nre;
+                        }
+                        vd[q] = on;
+                    } else if (q < nv) {
                         const int c = q / LL, rr = q - c * LL, x = rr / L, y = rr - x * L;
                         const float b = preact_visible_f(Ws, vbs, h, G, c, x, y);
                         bool near;
@@ -272,9 +310,9 @@ template __global__ void sweep_generic_kernel<1024>(SweepLaunch);
 template __global__ void sweep_generic_kernel<256>(SweepLaunch);
 template __global__ void sweep_generic_kernel<64>(SweepLaunch);
 
-size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks)
+size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense)
 {
-    return (size_t)generic_lds_layout(K, C, LW, L, target, banks).total;
+    return (size_t)generic_lds_layout(K, C, LW, L, target, banks, dense).total;
 }
 
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)

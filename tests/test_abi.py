@@ -43,9 +43,9 @@ def test_version(lib):
     assert "gfx950" in _lib.crbm_version()
 
 
-def _params(K=4, C=1, Lw=3, ptr=0x1000, open_cols=0, n_edge=0):
+def _params(K=4, C=1, Lw=3, ptr=0x1000, open_cols=0, n_edge=0, dense=0):
     from paper_2008_05401_amd import _lib
-    return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr, open_cols, n_edge)
+    return _lib.crbm_params(K, C, Lw, ptr, ptr, ptr, open_cols, n_edge, dense)
 
 
 def _desc(target=0, L=8, n=4, gk=1, rbm=None, boundary=0):
@@ -77,6 +77,14 @@ def test_workspace_size_validation(lib):
     assert _lib.crbm_workspace_size(_params(open_cols=2), _desc()) == 0
     assert _lib.crbm_workspace_size(_params(), _desc(boundary=2)) == 0
     assert _lib.crbm_workspace_size(_params(C=3, n_edge=1, open_cols=1), _desc(target=1, L=6, boundary=1)) > 0
+    # fully connected RBM: K up to 256, built for the job's L, no banks
+    assert _lib.crbm_workspace_size(_params(K=128, Lw=8, dense=1), _desc(target=1, L=8)) > 0
+    assert _lib.crbm_workspace_size(_params(K=257, Lw=8, dense=1), _desc(L=8)) == 0
+    assert _lib.crbm_workspace_size(_params(K=64, Lw=6, dense=1), _desc(L=8)) == 0            # Lw != L
+    assert _lib.crbm_workspace_size(_params(K=64, Lw=8, dense=1, n_edge=1), _desc(L=8)) == 0
+    assert _lib.crbm_workspace_size(_params(K=64, Lw=8, dense=2), _desc(L=8)) == 0
+    assert _lib.crbm_workspace_size(_params(K=256, C=3, Lw=12, dense=1), _desc(target=1, L=12)) == 0  # LDS
+    assert _lib.crbm_grad_workspace_size(_params(K=64, Lw=8, dense=1), 10) >= 10 * (64 * 64 + 64 + 64) * 8
     # Kitaev keeps the singular values of every chain: 4 chains x 36 doubles more
     kit = _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=6))
     assert kit >= _lib.crbm_workspace_size(_params(), _desc(L=6)) + 4 * 36 * 8
