@@ -28,11 +28,18 @@ struct ConvGeo {
     __device__ __forceinline__ int bank_size() const { return K * C * LW * LW; }
 };
 
+// Offsets b of the window that stay inside the lattice: all LW when the
+// columns wrap; with open columns the hidden window j..j+LW-1 ends at L-1 and
+// the visible unit y is reached from hidden columns y-b >= 0.  Loop bounds
+// instead of in-loop exits keep the inner loops branch-free.
+__device__ __forceinline__ int hidden_taps(const ConvGeo& G, int j) { return G.open ? min(G.LW, G.L - j) : G.LW; }
+__device__ __forceinline__ int visible_taps(const ConvGeo& G, int y) { return G.open ? min(G.LW, y + 1) : G.LW; }
+
 // FP64 hidden pre-activation of unit (k, i, j)
 __device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* hbs, const uint8_t* v,
                                                   const ConvGeo& G, int k, int i, int j)
 {
-    const int C = G.C, LW = G.LW, L = G.L;
+    const int C = G.C, LW = G.LW, L = G.L, nb = hidden_taps(G, j);
     const int bk = G.bank(j);
     const float* Wb = Ws + (size_t)bk * G.bank_size();
     double acc = (double)hbs[bk * G.K + k];
@@ -42,12 +49,9 @@ __device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* 
             if (ia >= L) ia -= L;
             const uint8_t* row = v + (c * L + ia) * L;
             const float* wr = Wb + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
+            for (int b = 0; b < nb; ++b) {
                 int jb = j + b;
-                if (jb >= L) {
-                    if (G.open) break;
-                    jb -= L;
-                }
+                if (jb >= L) jb -= L;
                 acc += (double)wr[b] * (double)row[jb];
             }
         }
@@ -59,21 +63,26 @@ __device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* 
 __device__ __forceinline__ double preact_visible_d(const float* Ws, const float* vbs, const uint8_t* h,
                                                    const ConvGeo& G, int c, int x, int y)
 {
-    const int K = G.K, C = G.C, LW = G.LW, L = G.L;
+    const int K = G.K, C = G.C, LW = G.LW, L = G.L, nb = visible_taps(G, y);
     double acc = (double)vbs[c];
     for (int k = 0; k < K; ++k)
         for (int a = 0; a < LW; ++a) {
             int xa = x - a;
             if (xa < 0) xa += L;
             const uint8_t* row = h + (k * L + xa) * L;
-            for (int b = 0; b < LW; ++b) {
-                int yb = y - b;
-                if (yb < 0) {
-                    if (G.open) break;
-                    yb += L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            if (G.ne == 0) {
+                for (int b = 0; b < nb; ++b) {
+                    int yb = y - b;
+                    if (yb < 0) yb += L;
+                    acc += (double)wr[b] * (double)row[yb];
                 }
-                const float w = Ws[(size_t)G.bank(yb) * G.bank_size() + ((k * C + c) * LW + a) * LW + b];
-                acc += (double)w * (double)row[yb];
+            } else {
+                for (int b = 0; b < nb; ++b) {
+                    int yb = y - b;
+                    if (yb < 0) yb += L;
+                    acc += (double)wr[(size_t)G.bank(yb) * G.bank_size() + b] * (double)row[yb];
+                }
             }
         }
     return acc;
@@ -83,7 +92,7 @@ __device__ __forceinline__ double preact_visible_d(const float* Ws, const float*
 __device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* hbs, const uint8_t* v, const ConvGeo& G,
                                                  int k, int i, int j)
 {
-    const int C = G.C, LW = G.LW, L = G.L;
+    const int C = G.C, LW = G.LW, L = G.L, nb = hidden_taps(G, j);
     const int bk = G.bank(j);
     const float* Wb = Ws + (size_t)bk * G.bank_size();
     float acc = hbs[bk * G.K + k];
@@ -93,12 +102,9 @@ __device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* h
             if (ia >= L) ia -= L;
             const uint8_t* row = v + (c * L + ia) * L;
             const float* wr = Wb + ((k * C + c) * LW + a) * LW;
-            for (int b = 0; b < LW; ++b) {
+            for (int b = 0; b < nb; ++b) {
                 int jb = j + b;
-                if (jb >= L) {
-                    if (G.open) break;
-                    jb -= L;
-                }
+                if (jb >= L) jb -= L;
                 acc = fmaf(wr[b], (float)row[jb], acc);
             }
         }
@@ -108,21 +114,26 @@ __device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* h
 __device__ __forceinline__ float preact_visible_f(const float* Ws, const float* vbs, const uint8_t* h, const ConvGeo& G,
                                                   int c, int x, int y)
 {
-    const int K = G.K, C = G.C, LW = G.LW, L = G.L;
+    const int K = G.K, C = G.C, LW = G.LW, L = G.L, nb = visible_taps(G, y);
     float acc = vbs[c];
     for (int k = 0; k < K; ++k)
         for (int a = 0; a < LW; ++a) {
             int xa = x - a;
             if (xa < 0) xa += L;
             const uint8_t* row = h + (k * L + xa) * L;
-            for (int b = 0; b < LW; ++b) {
-                int yb = y - b;
-                if (yb < 0) {
-                    if (G.open) break;
-                    yb += L;
+            const float* wr = Ws + ((k * C + c) * LW + a) * LW;
+            if (G.ne == 0) {
+                for (int b = 0; b < nb; ++b) {
+                    int yb = y - b;
+                    if (yb < 0) yb += L;
+                    acc = fmaf(wr[b], (float)row[yb], acc);
                 }
-                const float w = Ws[(size_t)G.bank(yb) * G.bank_size() + ((k * C + c) * LW + a) * LW + b];
-                acc = fmaf(w, (float)row[yb], acc);
+            } else {
+                for (int b = 0; b < nb; ++b) {
+                    int yb = y - b;
+                    if (yb < 0) yb += L;
+                    acc = fmaf(wr[(size_t)G.bank(yb) * G.bank_size() + b], (float)row[yb], acc);
+                }
             }
         }
     return acc;

@@ -15,6 +15,21 @@ __device__ __forceinline__ int bank_of_col(int j, int L, int ne)
     return j < ne ? 1 + j : (j >= L - ne ? 1 + ne + (j - (L - ne)) : 0);
 }
 
+// hidden columns [j0, j1) owned by filter bank `bank`
+__device__ __forceinline__ void bank_columns(int bank, int L, int ne, int& j0, int& j1)
+{
+    if (bank == 0) {
+        j0 = ne;
+        j1 = L - ne;
+    } else if (bank <= ne) {
+        j0 = bank - 1;
+        j1 = bank;
+    } else {
+        j0 = L - ne + (bank - ne - 1);
+        j1 = j0 + 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // F(x_b) of Eq. (free-energy_CRBM), FP64 terms and sums; one workgroup per state.
 // ---------------------------------------------------------------------------
@@ -38,6 +53,7 @@ __global__ __launch_bounds__(256) void free_energy_kernel(const float* __restric
     for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
         const int bk = bank_of_col(j, L, ne);
+        const int taps = open ? min(LW, L - j) : LW;  // window offsets inside the lattice
         double acc = hbd[bk * K + k];
         for (int c = 0; c < C; ++c)
             for (int a = 0; a < LW; ++a) {
@@ -45,12 +61,9 @@ __global__ __launch_bounds__(256) void free_energy_kernel(const float* __restric
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
                 const double* wr = Wd + bk * nW + ((k * C + c) * LW + a) * LW;
-                for (int b = 0; b < LW; ++b) {
+                for (int b = 0; b < taps; ++b) {
                     int jb = j + b;
-                    if (jb >= L) {
-                        if (open) break;
-                        jb -= L;
-                    }
+                    if (jb >= L) jb -= L;
                     acc += row[jb] ? wr[b] : 0.0;
                 }
             }
@@ -191,6 +204,7 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
     for (int q = threadIdx.x; q < K * LL; q += blockDim.x) {
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
         const int bk = bank_of_col(j, L, ne);
+        const int taps = open ? min(LW, L - j) : LW;
         float acc = hb[bk * K + k];
         for (int c = 0; c < C; ++c)
             for (int a = 0; a < LW; ++a) {
@@ -198,12 +212,9 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
                 const float* wr = Ws + bk * nW + ((k * C + c) * LW + a) * LW;
-                for (int b = 0; b < LW; ++b) {
+                for (int b = 0; b < taps; ++b) {
                     int jb = j + b;
-                    if (jb >= L) {
-                        if (open) break;
-                        jb -= L;
-                    }
+                    if (jb >= L) jb -= L;
                     acc = fmaf(wr[b], (float)row[jb], acc);
                 }
             }
@@ -218,26 +229,28 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
             const int bank = p / nW, pw = p - bank * nW;
             const int b = pw % LW, a = (pw / LW) % LW, c = (pw / (LW * LW)) % C, k = pw / (C * LW * LW);
             const float* sk = sg + k * LL;
+            // hidden columns of this bank whose tap b stays inside the lattice
+            int j0, j1;
+            bank_columns(bank, L, ne, j0, j1);
+            if (open) j1 = min(j1, L - b);
             for (int i = 0; i < L; ++i) {
                 int ia = i + a;
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
                 const float* srow = sk + i * L;
-                for (int j = 0; j < L; ++j) {
-                    if (bank_of_col(j, L, ne) != bank) continue;
+                for (int j = j0; j < j1; ++j) {
                     int jb = j + b;
-                    if (jb >= L) {
-                        if (open) continue;
-                        jb -= L;
-                    }
+                    if (jb >= L) jb -= L;
                     s += row[jb] ? (double)srow[j] : 0.0;
                 }
             }
         } else if (p < nb * (nW + K)) {
             const int q0 = p - nb * nW, bank = q0 / K, k = q0 - bank * K;
             const float* sk = sg + k * LL;
-            for (int q = 0; q < LL; ++q)
-                if (bank_of_col(q % L, L, ne) == bank) s += (double)sk[q];
+            int j0, j1;
+            bank_columns(bank, L, ne, j0, j1);
+            for (int i = 0; i < L; ++i)
+                for (int j = j0; j < j1; ++j) s += (double)sk[i * L + j];
         } else {
             const uint8_t* vc = v + (p - nb * (nW + K)) * LL;
             for (int q = 0; q < LL; ++q) s += (double)vc[q];
