@@ -160,7 +160,10 @@ typedef struct {
 typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
 
 /* Bytes of device workspace a job needs (per-chain records plus internal
- * buffers).  Returns 0 for invalid arguments. Host only, no device work. */
+ * buffers).  Returns 0 for invalid arguments. Host only, no device work.
+ * Kitaev jobs run up to L = 24: up to L = 12 the eigen-step keeps M^T M in
+ * LDS; beyond, the workspace also holds an N x N FP64 matrix per chain
+ * (N = L^2; 2.7 MB per chain at L = 24). */
 CRBM_API size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* desc);
 
 /* Create a job handle: copies `params`/`desc` (the pointed-to device buffers
@@ -237,7 +240,8 @@ CRBM_API crbm_status crbm_free_energy(const crbm_params* params, const int8_t* x
  *   exact); S_out ignored (may be NULL).
  * CRBM_KITAEV (C = 1 or 3): S_out[B] = sum_lambda log 2cosh(eps_lambda/(2 T[b]))
  *   (device FP64) over the N = L^2 singular values of M; T is device [B];
- *   E_out ignored. L <= 12 for Kitaev. */
+ *   E_out ignored. L <= 12 for Kitaev (this op has no workspace for the
+ *   larger eigen-step; jobs go to L = 24). */
 CRBM_API crbm_status target_energy(int32_t target, const int8_t* x, int32_t B, int32_t C, int32_t L,
                           int32_t boundary, const double J[3] /* host */, const double* T, int32_t* E_out,
                           double* S_out, void* stream);

@@ -112,7 +112,8 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
     if (d->target == CRBM_ISING && p->C != 1) return fail(CRBM_EINVAL, "Ising jobs need C=1 (got %d)", p->C);
-    if (d->target == CRBM_KITAEV && d->L > 12) return fail(CRBM_EUNSUPPORTED, "Kitaev supports L <= 12 (got %d)", d->L);
+    if (d->target == CRBM_KITAEV && d->L > kitaev_max_l())
+        return fail(CRBM_EUNSUPPORTED, "Kitaev jobs support L <= %d (got %d)", kitaev_max_l(), d->L);
     if (d->target == CRBM_GIBBS && d->rbm_state)
         return fail(CRBM_EINVAL, "a persistent CRBM replica needs a physical target (got CRBM_GIBBS)");
     Plan pl{};
@@ -139,12 +140,20 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // workspace: [job descriptor][one record per chain][Kitaev: singular values, n_chains x L^2 doubles]
+//            [Kitaev beyond L = 12: eigen-step scratch, n_chains x kitaev_scratch_bytes(L)]
 size_t records_end(int n_chains) { return round_up(kJobBytes + (size_t)n_chains * sizeof(ChainRec), 256); }
 
-size_t workspace_bytes_for(const crbm_batch_desc* d)
+size_t eps_end(const crbm_batch_desc* d)
 {
     size_t o = records_end(d->n_chains);
     if (d->target == CRBM_KITAEV) o += round_up((size_t)d->n_chains * d->L * d->L * sizeof(double), 256);
+    return o;
+}
+
+size_t workspace_bytes_for(const crbm_batch_desc* d)
+{
+    size_t o = eps_end(d);
+    if (d->target == CRBM_KITAEV) o += round_up((size_t)d->n_chains * kitaev_scratch_bytes(d->L), 256);
     return o;
 }
 
@@ -255,6 +264,9 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.rbm_state = desc->rbm_state;
     j.rec = c->rec;
     j.eps = desc->target == CRBM_KITAEV ? (double*)((char*)desc->workspace + records_end(desc->n_chains)) : nullptr;
+    j.kitA = (desc->target == CRBM_KITAEV && kitaev_scratch_bytes(desc->L) > 0)
+                 ? (double*)((char*)desc->workspace + eps_end(desc))
+                 : nullptr;
     j.J0 = desc->J[0];
     j.J1 = desc->J[1];
     j.J2 = desc->J[2];

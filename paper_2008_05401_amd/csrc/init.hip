@@ -77,13 +77,11 @@ __global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
         ising_em_block(v, L, J.boundary, (long long*)red, E, M);
     } else {
         const int N = LL;
-        double* A = kit;
-        ko = kitaev_weight_block(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], A, A + N * (N + 1) / 2,
-                                 A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N, A + N * (N + 1) / 2 + 3 * N,
-                                 red, A);
+        const KitaevBufs kb = kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_global_doubles(L) : nullptr, L);
+        ko = kitaev_weight_block(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], kb, red);
         // singular values of the initial state, kept for temperature swaps
         if (J.eps)
-            for (int q = tid; q < N; q += NT) J.eps[(size_t)g * N + q] = A[q];
+            for (int q = tid; q < N; q += NT) J.eps[(size_t)g * N + q] = kb.eps[q];
     }
     if (tid == 0) {
         ChainRec R{};

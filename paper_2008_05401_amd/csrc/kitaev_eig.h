@@ -5,7 +5,10 @@
 // GPU method (differs from a one-sided Jacobi SVD on purpose):
 //   1. A = M^T M is assembled directly from the bond variables (each white
 //      site has three black neighbours, so A has at most 7 non-zeros per row);
-//      A is held in LDS as a packed lower triangle (N(N+1)/2 doubles);
+//      up to L = 12 A is held in LDS as a packed lower triangle (N(N+1)/2
+//      doubles, 83 KiB at N = 144); for 12 < L <= 24 it no longer fits and is
+//      stored in full (N x N, row-major) in a per-chain global scratch, where
+//      every access of the reduction below is then a contiguous row;
 //   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e);
 //   3. every eigenvalue lambda_i of the tridiagonal matrix by trisection on
 //      the Sturm count (division-free recurrence), one thread per eigenvalue;
@@ -26,18 +29,70 @@ struct KitaevOut {
     double S, Ef, Cf;
 };
 
-// LDS needs: A[N(N+1)/2], d[N], e[N], hv[N], p[N] doubles and `red` (>= 16 doubles).
+constexpr int KITAEV_LDS_MAX_L = 12;  // A packed in LDS up to here
+constexpr int KITAEV_MAX_L = 24;      // A in a global scratch beyond
+
+__host__ __device__ inline bool kitaev_a_in_lds(int L) { return L <= KITAEV_LDS_MAX_L; }
+
+// doubles of the global scratch of one chain (0 when A lives in LDS)
+__host__ __device__ inline size_t kitaev_global_doubles(int L)
+{
+    const size_t N = (size_t)L * L;
+    return kitaev_a_in_lds(L) ? 0 : N * N;
+}
+
+// LDS region: [A packed, or the N eigenvalues when A is global | d | e | hv | p]
+__host__ __device__ inline size_t kitaev_lds_bytes(int L)
+{
+    const size_t N = (size_t)L * L;
+    return sizeof(double) * ((kitaev_a_in_lds(L) ? N * (N + 1) / 2 : N) + 4 * N);
+}
+
+struct KitaevBufs {
+    double *A, *d, *e, *hv, *p, *eps;
+};
+
+// buffers inside the LDS region `lds`; `a_global` is the chain's scratch of
+// kitaev_global_doubles(L) doubles (unused up to L = 12).  eps aliases A in
+// LDS (A is dead once the tridiagonal form is known).
+__device__ inline KitaevBufs kitaev_bufs(double* lds, double* a_global, int L)
+{
+    const int N = L * L;
+    const int first = kitaev_a_in_lds(L) ? N * (N + 1) / 2 : N;
+    KitaevBufs b;
+    b.A = kitaev_a_in_lds(L) ? lds : a_global;
+    b.d = lds + first;
+    b.e = b.d + N;
+    b.hv = b.e + N;
+    b.p = b.hv + N;
+    b.eps = lds;
+    return b;
+}
+
+// Element (i, j) of A, i >= j for the packed form
+template <bool kFull>
+__device__ __forceinline__ int a_at(int i, int j, int N)
+{
+    return kFull ? i * N + j : tri(i, j);
+}
+
 // v: 0/1 bytes of the proposal, C channels ([3][L][L] = x,y,z bonds, or [1][L][L] = z bonds).
 // open_cols (Sec. IV.B): the x bonds from column L-1 to column 0 are absent.
-__device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
-                                         double Jz, double beta, double* A, double* d, double* e, double* hv,
-                                         double* p, double* red, double* eps_out = nullptr)
+// kFull: A stored in full (N x N) rather than as a packed lower triangle.
+template <bool kFull>
+__device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
+                                           double Jz, double beta, double* A, double* d, double* e, double* hv,
+                                           double* p, double* red, double* eps_out)
 {
     const int N = L * L;
     const int tid = threadIdx.x, nt = blockDim.x;
-    // 1. A = M^T M, row w owned by one thread
-    for (int w = tid; w < N; w += nt) {
-        for (int q = 0; q <= w; ++q) A[tri(w, q)] = 0.0;
+    // 1. A = M^T M, row w owned by one thread (full form: its mirror image too)
+    if (kFull) {
+        for (int q = tid; q < N * N; q += nt) A[q] = 0.0;
+    } else {
+        for (int w = tid; w < N; w += nt) {
+            for (int q = 0; q <= w; ++q) A[tri(w, q)] = 0.0;
+        }
     }
     __syncthreads();
     for (int w = tid; w < N; w += nt) {
@@ -81,7 +136,9 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int ope
                 double mbw2 = 0.0;
                 for (int s = 0; s < 3; ++s)
                     if (wn[s] == w2) mbw2 += wv[s];
-                A[tri(w, w2)] += mbw * mbw2;
+                A[a_at<kFull>(w, w2, N)] += mbw * mbw2;
+                // A[w2][w] (w2 < w) is written by this thread only: thread w2 fills columns <= w2
+                if (kFull && w2 != w) A[w2 * N + w] += mbw * mbw2;
             }
         }
     }
@@ -109,27 +166,48 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int ope
         for (int w = 0; w < nw; ++w) t += r[w];
         return t;
     };
+    // column k below the diagonal: in the full form read as row k (symmetry)
+    auto col = [&](int i, int k) -> double { return kFull ? A[k * N + i] : A[tri(i, k)]; };
     for (int k = 0; k + 2 < N; ++k) {
         double s2 = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) {
-            const double x = A[tri(i, k)];
+            const double x = col(i, k);
             s2 += x * x;
         }
         s2 = reduce(s2);
-        const double x0 = A[tri(k + 1, k)];
+        const double x0 = col(k + 1, k);
         const double rest = s2 - x0 * x0;
         if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
             if (tid == 0) {
-                d[k] = A[tri(k, k)];
+                d[k] = A[a_at<kFull>(k, k, N)];
                 e[k] = x0;
             }
             continue;
         }
         const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
         const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
-        for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : A[tri(i, k)];
+        for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : col(i, k);
         __syncthreads();
-        // p = bet * A22 v; row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
+        // p = bet * A22 v; full form: row i of A22 is contiguous
+        if (kFull) {
+            for (int i = k + 1 + grp; i < N; i += ngrp) {
+                const double* row = A + (size_t)i * N;
+                double a0 = 0.0, a1 = 0.0;
+                int j = k + 1 + gl;
+                for (; j + G < N; j += 2 * G) {
+                    a0 += row[j] * hv[j];
+                    a1 += row[j + G] * hv[j + G];
+                }
+                if (j < N) a0 += row[j] * hv[j];
+                double acc = a0 + a1;
+                acc += swz_xor<8>(acc);
+                acc += swz_xor<4>(acc);
+                acc += swz_xor<2>(acc);
+                acc += swz_xor<1>(acc);
+                if (gl == 0) p[i] = bet * acc;
+            }
+        } else
+        // packed form, row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
         for (int i = k + 1 + grp; i < N; i += ngrp) {
             const int rb = tri(i, 0);
             double a0 = 0.0, a1 = 0.0;
@@ -156,40 +234,40 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int ope
         double pv = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) pv += p[i] * hv[i];
         const double kk2 = bet * reduce(pv);  // 2 kk
-        // A22 -= v p^T + p v^T - 2 kk v v^T (lower triangle); a lane keeps the
-        // column values p_j, v_j of its (at most three) columns in registers
-        // (N <= 192; the callers allow L <= 12, N <= 144)
-        {
+        // A22 -= v p^T + p v^T - 2 kk v v^T (the lower triangle, or all of it
+        // in the full form); a lane keeps the column values p_j, v_j of three
+        // columns in registers per pass, a pass per 192 columns
+        for (int c0 = 0; k + 1 + 64 * c0 < N; c0 += 3) {
             double pj[3], vj[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const int j = k + 1 + lane + 64 * c;
+                const int j = k + 1 + lane + 64 * (c0 + c);
                 pj[c] = j < N ? p[j] : 0.0;
                 vj[c] = j < N ? hv[j] : 0.0;
             }
             for (int i = k + 1 + wid; i < N; i += nw) {
-                const int rb = tri(i, 0);
+                const int rb = kFull ? i * N : tri(i, 0);
                 const double vi = hv[i], pi = p[i];
                 const double ci = pi - kk2 * vi;  // p_i - 2 kk v_i
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const int j = k + 1 + lane + 64 * c;
-                    if (j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
+                    const int j = k + 1 + lane + 64 * (c0 + c);
+                    if (kFull ? j < N : j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
                 }
             }
         }
         if (tid == 0) {
-            d[k] = A[tri(k, k)];
+            d[k] = A[a_at<kFull>(k, k, N)];
             e[k] = alpha;
         }
         __syncthreads();
     }
     if (tid == 0) {
         if (N >= 2) {
-            d[N - 2] = A[tri(N - 2, N - 2)];
-            e[N - 2] = A[tri(N - 1, N - 2)];
+            d[N - 2] = A[a_at<kFull>(N - 2, N - 2, N)];
+            e[N - 2] = A[a_at<kFull>(N - 1, N - 2, N)];
         }
-        d[N - 1] = A[tri(N - 1, N - 1)];
+        d[N - 1] = A[a_at<kFull>(N - 1, N - 1, N)];
     }
     __syncthreads();
     double* ee = hv;  // e^2, hv is free now
@@ -274,7 +352,7 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int ope
         }
         const double lam = 0.5 * (lo + hi);
         const double eps = sqrt(lam > 0.0 ? lam : 0.0);
-        if (eps_out) eps_out[idx] = eps;  // may alias A: A is dead after the tridiagonalisation
+        if (eps_out) eps_out[idx] = eps;  // may alias a packed A: it is dead after the tridiagonalisation
         const double xv = 0.5 * beta * eps;
         S += log2cosh_d(xv);
         Ef -= 0.5 * eps * tanh(xv);
@@ -288,10 +366,13 @@ __device__ KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int ope
     return o;
 }
 
-__host__ __device__ inline size_t kitaev_lds_bytes(int L)
+// S, E_f, C_f of the proposal v; the eigenvalues eps_lambda go to b.eps
+__device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
+                                                double Jz, double beta, const KitaevBufs& b, double* red)
 {
-    const size_t N = (size_t)L * L;
-    return sizeof(double) * (N * (N + 1) / 2 + 4 * N);
+    if (kitaev_a_in_lds(L))
+        return kitaev_weight_block_t<false>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps);
+    return kitaev_weight_block_t<true>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps);
 }
 
 }  // namespace crbm

@@ -163,9 +163,9 @@ __global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __res
     const int8_t* xs = x + (size_t)blockIdx.x * C * N;
     for (int q = threadIdx.x; q < C * N; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
-    const KitaevOut o = kitaev_weight_block(v, C, L, open_cols, Jx, Jy, Jz, 1.0 / T[blockIdx.x], A, A + N * (N + 1) / 2,
-                                            A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
-                                            A + N * (N + 1) / 2 + 3 * N, red);
+    // the stand-alone op keeps A in LDS (L <= 12)
+    const KitaevOut o = kitaev_weight_block(v, C, L, open_cols, Jx, Jy, Jz, 1.0 / T[blockIdx.x],
+                                            kitaev_bufs(A, nullptr, L), red);
     if (threadIdx.x == 0) S[blockIdx.x] = o.S;
 }
 

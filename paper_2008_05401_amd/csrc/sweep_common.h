@@ -19,6 +19,7 @@ struct JobDev {
     ChainRec* rec;
     double* eps;        // Kitaev: singular values of every chain's current state [n_chains][L*L]
     double* trace;      // per-sweep energy ring buffer [n_chains][trace_len] or nullptr
+    double* kitA;       // Kitaev beyond L = 12: per-chain global scratch of the eigen-step
     double J0, J1, J2;
     uint64_t seed;
     int K, C, LW, target, L, n_chains, gibbs_k, burnin;
@@ -46,6 +47,9 @@ struct SweepLaunch {
 };
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense);
+// Kitaev eigen-step: largest L, and global scratch bytes per chain (0 while A fits in LDS)
+int kitaev_max_l();
+size_t kitaev_scratch_bytes(int L);
 hipError_t launch_autocorr(const double* trace, int n, int len, int start, int max_lag, double c_win, double* out,
                            double* tau, int* window, hipStream_t s);
 hipError_t launch_tempering_swap(const JobDev* job_dev, int n_pairs, int n_ladders, int q0, uint32_t round,

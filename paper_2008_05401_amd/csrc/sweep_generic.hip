@@ -239,11 +239,9 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
         KitaevOut ko{0.0, 0.0, 0.0};
         if (ising) ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
         else {
-            double* A = kit;
-            const int N = LL;
-            ko = kitaev_weight_block(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, A, A + N * (N + 1) / 2,
-                                     A + N * (N + 1) / 2 + N, A + N * (N + 1) / 2 + 2 * N,
-                                     A + N * (N + 1) / 2 + 3 * N, red, kit);
+            const KitaevBufs kb =
+                kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_global_doubles(L) : nullptr, L);
+            ko = kitaev_weight_block(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
         }
         if (tid == 0) {
             const double logr = ising ? (-beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F)) : ((ko.S - R.S) + (Fp - R.F));
@@ -309,6 +307,10 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 template __global__ void sweep_generic_kernel<1024>(SweepLaunch);
 template __global__ void sweep_generic_kernel<256>(SweepLaunch);
 template __global__ void sweep_generic_kernel<64>(SweepLaunch);
+
+int kitaev_max_l() { return KITAEV_MAX_L; }
+
+size_t kitaev_scratch_bytes(int L) { return kitaev_global_doubles(L) * sizeof(double); }
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense)
 {

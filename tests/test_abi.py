@@ -66,7 +66,9 @@ def test_workspace_size_validation(lib):
     assert _lib.crbm_workspace_size(_params(), _desc(n=0)) == 0
     assert _lib.crbm_workspace_size(_params(), _desc(gk=0)) == 0
     assert _lib.crbm_workspace_size(_params(), _desc(L=257)) == 0
-    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=13)) == 0
+    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=25)) == 0
+    # beyond L = 12 the Kitaev eigen-step keeps an N x N FP64 matrix per chain in the workspace
+    assert _lib.crbm_workspace_size(_params(C=3), _desc(target=1, L=16)) >= 4 * 256 * 256 * 8
     assert _lib.crbm_workspace_size(_params(), _desc(target=2, rbm=0x1000)) == 0  # replica needs a target
     assert _lib.crbm_workspace_size(_params(C=3), _desc(target=2)) > 0            # Gibbs-only chains, C = 3
     assert _lib.crbm_workspace_size(_params(), _desc(rbm=0x1000)) > 0
@@ -100,8 +102,10 @@ def test_init_rejects_before_device_work(lib):
     d.workspace_bytes = 16
     st = L.crbm_init(ct.byref(ctx), ct.byref(_params()), ct.byref(d), None)
     assert st == _lib.CRBM_EBUDGET
-    st = L.crbm_init(ct.byref(ctx), ct.byref(_params(C=3)), ct.byref(_desc(target=1, L=16)), None)
+    st = L.crbm_init(ct.byref(ctx), ct.byref(_params(C=3)), ct.byref(_desc(target=1, L=25)), None)
     assert st == _lib.CRBM_EUNSUPPORTED
+    st = L.crbm_init(ct.byref(ctx), ct.byref(_params(C=3)), ct.byref(_desc(target=1, L=16)), None)
+    assert st == _lib.CRBM_EBUDGET   # 1 MiB of workspace is short of the L=16 eigen-step scratch
 
 
 def test_other_entry_points_validate(lib):

@@ -208,4 +208,4 @@ def test_invalid_arguments_raise(api):
     with pytest.raises(_lib.CRBMError):
         api.Job(_p(api, f3), 0, 8, np.full(2, 2.0))          # Ising with C=3
     with pytest.raises(_lib.CRBMError):
-        api.Job(_p(api, f3), 1, 16, np.full(2, 0.1))         # Kitaev L > 12
+        api.Job(_p(api, f3), 1, 25, np.full(2, 0.1))         # Kitaev jobs stop at L = 24
