@@ -44,6 +44,12 @@ MEASURED_TRAFFIC = {"sources_sha256": "c0a0ad5536959c674536e86562daa962b8b6e647b
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
                     "fetch_kib": 9313.9, "fetch_scale": 2.0, "write_kib": 20115.0, "write_scale": 1.0}
 
+# VALU issue of the same kernel from SQ counters (rocprofv3 --pmc SQ_INSTS_VALU ... GRBM_GUI_ACTIVE),
+# reported while the kernel sources hash to the measured ones
+MEASURED_VALU = {"sources_sha256": "d0933c9d9b238a77d17e7395cc947922d7c2c331e9e9f0b6ec1545cd70d09c2d",
+                 "valu_wave_instr_per_site_sweep": 7.765, "valu_issue_fraction": 1.08,
+                 "lds_bank_conflicts_per_access": 8.9e-4}
+
 
 def kernel_sources_sha256():
     import hashlib
@@ -511,6 +517,12 @@ def main():
     lds_tbs = lds_table_bytes_per_site_sweep(K, C, Lw) * n * L * L * sweeps_per_launch / avg_launch_s / 1e12
     out["lds"] = {"table_bytes_per_site_sweep": lds_table_bytes_per_site_sweep(K, C, Lw), "achieved": lds_tbs,
                   "peak": PEAK_LDS_TBS, "unit": "TB/s", "frac": lds_tbs / PEAK_LDS_TBS}
+    # the binding resource: VALU issue slots (one wave64 instruction per 4 cycles per SIMD)
+    if kernel_sources_sha256() == MEASURED_VALU["sources_sha256"]:
+        out["valu_issue"] = {k: v for k, v in MEASURED_VALU.items() if k != "sources_sha256"}
+        out["valu_issue"]["source"] = "profiles/sweep_ising_L64_batched_sq_counters.md"
+    else:
+        out["valu_issue"] = None
     if not args.no_extra:
         out["kitaev"] = kitaev()
         out["autocorrelation"] = autocorrelation_times()
