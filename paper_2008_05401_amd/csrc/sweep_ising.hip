@@ -256,10 +256,34 @@ __device__ __forceinline__ double preact_v_exact(const float* __restrict__ W, fl
 // taps are read by every lane at the same address.
 template <int LW>
 __device__ double free_energy_exact(const float* Wl, const float* hbl, float vb, const uint32_t* pl, int RS, int L,
-                                    int K, double* red, const double* dc)
+                                    int K, double* red, const double* dc, const double* T64)
 {
     const int LL = L * L, lgL = 31 - __builtin_clz(L), Lm = L - 1;
     double f = 0.0;
+    if (T64) {
+        // FP64 subset sums of the filter rows: a = h_b + sum_a T64[k][a][window bits]; the
+        // softplus terms of a site in product form, sum_k max(a, 0) + log prod_k (1 + e^{-|a|})
+        // (each factor in (1, 2], so the product of K <= 64 of them stays in range)
+        constexpr int NP = 1 << LW;
+        for (int q = threadIdx.x; q < LL; q += blockDim.x) {
+            const int i = q >> lgL, j = q & Lm;
+            uint32_t wb[LW];
+#pragma unroll
+            for (int a = 0; a < LW; ++a) wb[a] = window32(pl + ((i + a) & Lm) * RS, j) & (NP - 1);
+            double pos = 0.0, prod = 1.0;
+            for (int k = 0; k < K; ++k) {
+                const double* Tk = T64 + k * LW * NP;
+                double acc = (double)hbl[k];
+#pragma unroll
+                for (int a = 0; a < LW; ++a) acc += Tk[a * NP + wb[a]];
+                pos += acc > 0.0 ? acc : 0.0;
+                prod *= 1.0 + exp_c(-fabs(acc), dc);
+            }
+            f -= pos + log_c(prod, dc);
+            if (bit_at(pl + i * RS, j)) f -= (double)vb;
+        }
+        return block_sum(f, red);
+    }
     for (int k = 0; k < K; ++k) {
         const float* Wk = Wl + k * LW * LW;
         const double hb = (double)hbl[k];
@@ -446,6 +470,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
     double* red = (double*)(smem + (((size_t)(3 * tsz + 7 * K + K * LW * LW) * 4 + 15) & ~(size_t)15));
     uint32_t* vpl = (uint32_t*)(red + 64);
     uint32_t* hpl = vpl + 3 * PL;
+    // FP64 subset sums of the filter rows for the exact free energy, when small enough
+    double* T64 = ising_fast_t64(K, LW) ? (double*)(((uintptr_t)(hpl + K * PL) + 7) & ~(uintptr_t)7) : nullptr;
     __shared__ float sh_vb, sh_dAv, sh_vb_raw, sh_evbm, sh_Sv;
     __shared__ long long sh_t0;
     __shared__ int sh_flag;
@@ -510,6 +536,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             T1[idx] = (float)exp(-d1);
             T2[idx] = (float)exp(-d2);
             E1p[idx] = (float)exp(d1);
+            if (T64) T64[idx] = d1;
         } else {
             float s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -520,6 +547,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
             }
             T1[idx] = s1 * NLOG2E;
             T2[idx] = s2 * NLOG2E;
+            if (T64) {
+                double d1 = 0.0;
+#pragma unroll
+                for (int b = 0; b < LW; ++b)
+                    if ((p >> b) & 1) d1 += (double)wr[b];
+                T64[idx] = d1;
+            }
         }
     }
     for (int k = tid; k < K; k += NT) {
@@ -902,9 +936,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         double Fnew = Fp, Bnew = Bp, Fold = 0.0;
         if (flag == 2) {
             // inside the float32 band: decide with FP64 free energies of both states
-            Fnew = free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vp, RS, L, K, red, sh_dc);
+            Fnew = free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vp, RS, L, K, red, sh_dc, T64);
             // the cached F of the current state is already exact after an earlier re-check
-            Fold = sh_Bcur > 0.0 ? free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vpl + cur * PL, RS, L, K, red, sh_dc)
+            Fold = sh_Bcur > 0.0 ? free_energy_exact<LW>(Wl, hbl, sh_vb_raw, vpl + cur * PL, RS, L, K, red, sh_dc, T64)
                                  : R.F;
             Bnew = 0.0;
             if (tid == 0) {
@@ -983,6 +1017,7 @@ size_t ising_fast_lds_bytes(int K, int LW, int L)
     o += 64 * 8;
     const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
     o += (3 + (size_t)K) * (size_t)L * RS * 4;
+    if (ising_fast_t64(K, LW)) o = ((o + 7) & ~(size_t)7) + tsz * sizeof(double);
     return o;
 }
 
