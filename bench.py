@@ -96,6 +96,13 @@ def cpu_baseline(f, T, L, seed, seconds=15.0):
     t0 = time.perf_counter()
     ch.run(sweeps)
     dt = time.perf_counter() - t0
+    # the small configuration at its full size (L=8, 64 chains, 2000 sweeps) fits the oracle whole
+    fs = WL_small_filters()
+    chs = oracle.Chains(oracle.CRBM(fs.W, fs.hbias, fs.vbias), oracle.ISING, 8, np.full(64, 2.269), seed=0,
+                        burnin=200)
+    t1 = time.perf_counter()
+    chs.run(2000)
+    small_s = time.perf_counter() - t1
     return {
         "value": n * L * L * sweeps / dt,
         "unit": "site-sweeps/s",
@@ -103,7 +110,32 @@ def cpu_baseline(f, T, L, seed, seconds=15.0):
         "kind": "oracle",
         "sample": f"chains 0-{n - 1} of the 4096-chain L=64 batch (T=1.5 and 1.565), {sweeps} sweeps after 1 "
                   f"untimed sweep, FP64 C oracle with OpenMP over chains, {dt:.1f} s",
+        "small_config_full_size_s": small_s,
     }
+
+
+def WL_small_filters():
+    from paper_2008_05401_amd import workloads as WL
+    return WL.random_filters(4, 1, 3, 0.1, seed=0)
+
+
+def small_config(sweeps=2000, burnin=200):
+    """The small Ising configuration at full size: L=8, K=4 3x3 filters ~ N(0, 0.1),
+    T=2.269, 64 chains, 2000 sweeps with 200 of burn-in, in one launch;
+    latency-bound, so the wall time of the whole run is the figure."""
+    import torch
+
+    from paper_2008_05401_amd import api
+    job = api.Job(api.CRBMParams.from_filters(WL_small_filters()), api.ISING, 8, np.full(64, 2.269), seed=0,
+                  burnin=burnin)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job.run(sweeps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = job.stats()
+    return {"wall_s": wall, "site_sweeps_per_s": 64 * 64 * sweeps / wall,
+            "acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
 
 
 def served(n_jobs, rate, warmup_s, n_sweeps, plain_jobs):
@@ -551,6 +583,7 @@ def main():
         out["autocorrelation"] = autocorrelation_times()
         out["frbm"] = frbm()
         out["analytic_per_temperature"] = analytic_per_temperature()
+        out["small_config"] = small_config()
         out["tempering"] = tempering()
         out["training"] = training_and_transfer()
         out["kitaev_training"] = kitaev_training_and_transfer()

@@ -184,9 +184,24 @@ __device__ inline double free_energy_block(const float* Ws, const float* hbs, co
         for (int q = threadIdx.x; q < nv; q += blockDim.x) fl -= (double)vbs[q] * (double)v[q];
         return block_sum(fl, red);
     }
-    for (int q = threadIdx.x; q < G.K * LL; q += blockDim.x) {
-        const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
-        fl -= softplus_d(preact_hidden_d(Ws, hbs, v, G, k, i, j));
+    if (LL >= (int)blockDim.x) {
+        // a lane per site: the K softplus terms in product form, sum_k max(a, 0) +
+        // log prod_k (1 + e^{-|a|}), one log per site (each factor in (1, 2], K <= 64)
+        for (int r = threadIdx.x; r < LL; r += blockDim.x) {
+            const int i = r / L, j = r - i * L;
+            double pos = 0.0, prod = 1.0;
+            for (int k = 0; k < G.K; ++k) {
+                const double a = preact_hidden_d(Ws, hbs, v, G, k, i, j);
+                pos += a > 0.0 ? a : 0.0;
+                prod *= 1.0 + exp(-fabs(a));
+            }
+            fl -= pos + log(prod);
+        }
+    } else {
+        for (int q = threadIdx.x; q < G.K * LL; q += blockDim.x) {
+            const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
+            fl -= softplus_d(preact_hidden_d(Ws, hbs, v, G, k, i, j));
+        }
     }
     for (int q = threadIdx.x; q < G.C * LL; q += blockDim.x) fl -= (double)vbs[q / LL] * (double)v[q];
     return block_sum(fl, red);
