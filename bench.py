@@ -40,15 +40,15 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 # after any change to them `traffic` is reported as null until re-measured.
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
                   "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": "c0a0ad5536959c674536e86562daa962b8b6e647b1c730425a1a491f705fdaf5",
+MEASURED_TRAFFIC = {"sources_sha256": "6358d54c730092f6f50c87e911db31ac3f71fea178718b92d0d60033a467f5b8",
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
-                    "fetch_kib": 9313.9, "fetch_scale": 2.0, "write_kib": 20115.0, "write_scale": 1.0}
+                    "fetch_kib": 9763.5, "fetch_scale": 2.0, "write_kib": 24215.6, "write_scale": 1.0}
 
 # VALU issue of the same kernel from SQ counters (rocprofv3 --pmc SQ_INSTS_VALU ... GRBM_GUI_ACTIVE),
 # reported while the kernel sources hash to the measured ones
-MEASURED_VALU = {"sources_sha256": "d0933c9d9b238a77d17e7395cc947922d7c2c331e9e9f0b6ec1545cd70d09c2d",
-                 "valu_wave_instr_per_site_sweep": 7.765, "valu_issue_fraction": 1.08,
-                 "lds_bank_conflicts_per_access": 8.9e-4}
+MEASURED_VALU = {"sources_sha256": "6358d54c730092f6f50c87e911db31ac3f71fea178718b92d0d60033a467f5b8",
+                 "valu_wave_instr_per_site_sweep": 7.755, "valu_issue_fraction": 1.09,
+                 "lds_bank_conflicts_per_access": 8.9e-04}
 
 
 def kernel_sources_sha256():
