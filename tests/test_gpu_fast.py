@@ -202,3 +202,25 @@ def test_gibbs_only_target(orc, api, L, K, Lw):
     assert np.all(st["n_acc"] == 7)
     for name in ("E", "sumE", "sumM2"):
         assert np.array_equal(st[name], ch.rec[name])
+
+
+def test_transfer_shape_sampled_chains(orc, api):
+    # the transfer-sampling launch (L=128, 2048 chains) with the exact kernel zero-padded to
+    # K=8 5x5 (acceptance ~1, so the FP64 MH re-check path runs); sampled chains recomputed
+    # one by one by the oracle from their chain index
+    L, n, T = 128, 2048, 2.3
+    f = WL.analytic_ising_filters(T, K=8, Lw=5)
+    job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, np.full(n, T), seed=1)
+    job.run(4)
+    st = job.stats()
+    state = job.state.cpu().numpy()
+    assert st["n_acc"].sum() > 0.9 * n * 4
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    for g in (0, 1023, 2047):
+        ch = orc.Chains(m, orc.ISING, L, np.full(1, T), seed=1, g0=g)
+        ch.run(4)
+        assert ch.ties[0] == 0 and ch.ties[1] == 0
+        assert np.array_equal(state[g], ch.state[0])
+        for name in ("n_acc", "E", "sumE", "sumM2"):
+            assert st[name][g] == ch.rec[name][0]
+        assert abs(st["F"][g] - ch.rec["F"][0]) <= st["F_bound"][g] + 1e-9 * abs(ch.rec["F"][0])
