@@ -471,7 +471,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); chains are independent, so the "
-              f"path shards across GPUs without communication, but this build measures one GPU only.",
+              f"path shards across GPUs without communication; this benchmark measures one GPU only.",
               file=sys.stderr)
         sys.exit(2)
 

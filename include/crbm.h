@@ -66,7 +66,7 @@ typedef enum {
     CRBM_EINVAL = -1,      /* invalid argument (shape, size, null pointer, range) */
     CRBM_EBUDGET = -2,     /* workspace too small */
     CRBM_EHIP = -3,        /* a HIP runtime call failed */
-    CRBM_EUNSUPPORTED = -4 /* valid but not supported by this build (e.g. LDS too small) */
+    CRBM_EUNSUPPORTED = -4 /* valid but not supported by this library (e.g. LDS too small) */
 } crbm_status;
 
 /* CRBM_GIBBS: no target; every proposal is accepted, so the chain is the plain
