@@ -41,15 +41,21 @@ __host__ __device__ inline size_t kitaev_global_doubles(int L)
     return kitaev_a_in_lds(L) ? 0 : N * N;
 }
 
-// LDS region: [A packed, or the N eigenvalues when A is global | d | e | hv | p]
+// panel width of the blocked reduction used when A is global
+constexpr int KITAEV_NB = 8;
+
+// LDS region: [A packed, or the N eigenvalues when A is global | d | e | hv | p | (A global:)
+// the panel's reflectors V and their companions W, column-major, KITAEV_NB x N each, then
+// 16 waves x 2 KITAEV_NB partial sums and 2 KITAEV_NB reduced ones]
 __host__ __device__ inline size_t kitaev_lds_bytes(int L)
 {
     const size_t N = (size_t)L * L;
-    return sizeof(double) * ((kitaev_a_in_lds(L) ? N * (N + 1) / 2 : N) + 4 * N);
+    return sizeof(double) * (kitaev_a_in_lds(L) ? N * (N + 1) / 2 + 4 * N
+                                                : 5 * N + 2 * (size_t)KITAEV_NB * N + 34 * (size_t)KITAEV_NB);
 }
 
 struct KitaevBufs {
-    double *A, *d, *e, *hv, *p, *eps;
+    double *A, *d, *e, *hv, *p, *eps, *vw;
 };
 
 // buffers inside the LDS region `lds`; `a_global` is the chain's scratch of
@@ -66,6 +72,7 @@ __device__ inline KitaevBufs kitaev_bufs(double* lds, double* a_global, int L)
     b.hv = b.e + N;
     b.p = b.hv + N;
     b.eps = lds;
+    b.vw = kitaev_a_in_lds(L) ? nullptr : b.p + N;
     return b;
 }
 
@@ -82,7 +89,7 @@ __device__ __forceinline__ int a_at(int i, int j, int N)
 template <bool kFull>
 __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
                                            double Jz, double beta, double* A, double* d, double* e, double* hv,
-                                           double* p, double* red, double* eps_out)
+                                           double* p, double* red, double* eps_out, double* vw)
 {
     const int N = L * L;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -168,6 +175,134 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     };
     // column k below the diagonal: in the full form read as row k (symmetry)
     auto col = [&](int i, int k) -> double { return kFull ? A[k * N + i] : A[tri(i, k)]; };
+    if constexpr (kFull) {
+        // Blocked reduction (the A in global memory): panels of NB columns.  Within
+        // a panel A keeps its values from the panel's start; column k is corrected
+        // on the fly by the panel's earlier reflectors,
+        //   a = A[:,k] - V W[k,:]^T - W V[k,:]^T,
+        // the matrix-vector product likewise, p = bet (A22 v - V (W^T v) - W (V^T v)),
+        // and w = p - kk v (kk = bet (p.v) / 2) joins W; after the panel one pass
+        // applies A22 -= V W^T + W V^T.  One read of the trailing matrix per column
+        // plus one read-write per panel, instead of three passes per column.
+        constexpr int NB = KITAEV_NB;
+        double* Vc = vw;           // V[l][i] = vw[l N + i]
+        double* Wc = vw + NB * N;  // W[l][i]
+        double* part = vw + 2 * NB * N;  // per-wave partial sums of t_W, t_V: [16 waves][2 NB]
+        double* tvw = part + 32 * NB;    // t_W[l], t_V[l] (2 NB doubles) after their reduction
+        for (int k0 = 0; k0 + 2 < N; k0 += NB) {
+            const int nbk = min(NB, N - 2 - k0);
+            for (int jj = 0; jj < nbk; ++jj) {
+                const int k = k0 + jj;
+                // corrected column k, rows i >= k: diagonal to d[k], the rest to hv
+                double s2 = 0.0;
+                for (int i = k + tid; i < N; i += nt) {
+                    double a = A[(size_t)k * N + i];
+                    for (int l = 0; l < jj; ++l)
+                        a -= Vc[l * N + i] * Wc[l * N + k] + Wc[l * N + i] * Vc[l * N + k];
+                    if (i == k) {
+                        d[k] = a;
+                    } else {
+                        hv[i] = a;
+                        s2 += a * a;
+                    }
+                }
+                s2 = reduce(s2);  // also publishes hv and d[k]
+                const double x0 = hv[k + 1];
+                const double rest = s2 - x0 * x0;
+                if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
+                    // nothing to annihilate: the reflector is the identity
+                    for (int i = tid; i < N; i += nt) {
+                        Vc[jj * N + i] = 0.0;
+                        Wc[jj * N + i] = 0.0;
+                    }
+                    if (tid == 0) e[k] = x0;
+                    __syncthreads();
+                    continue;
+                }
+                const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
+                const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
+                if (tid == 0) e[k] = alpha;
+                // v into column jj of V (hv stays as read: other waves may still be
+                // reading x0 from it); per-thread shares of t_W = W^T v and t_V = V^T v
+                double* vcol = Vc + jj * N;
+                double tw[NB], tv[NB];
+#pragma unroll
+                for (int l = 0; l < NB; ++l) tw[l] = tv[l] = 0.0;
+                for (int i = tid; i < N; i += nt) {
+                    const double vi = i > k ? (i == k + 1 ? x0 - alpha : hv[i]) : 0.0;
+                    Vc[jj * N + i] = vi;
+                    if (i > k) {
+#pragma unroll
+                        for (int l = 0; l < NB; ++l)
+                            if (l < jj) {
+                                tw[l] += Wc[l * N + i] * vi;
+                                tv[l] += Vc[l * N + i] * vi;
+                            }
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < NB; ++l)
+                    if (l < jj) {
+                        const double a = wave_sum(tw[l]), b = wave_sum(tv[l]);
+                        if (lane == 0) {
+                            part[wid * 2 * NB + l] = a;
+                            part[wid * 2 * NB + NB + l] = b;
+                        }
+                    }
+                __syncthreads();
+                if (tid < 2 * jj) {
+                    const int slotl = tid < jj ? tid : NB + (tid - jj);
+                    double t = 0.0;
+                    for (int w = 0; w < nw; ++w) t += part[w * 2 * NB + slotl];
+                    tvw[slotl] = t;
+                }
+                __syncthreads();
+                // p = bet (A22 v - V t_W - W t_V), rows of A22 contiguous; G lanes per row
+                double pvl = 0.0;
+                for (int i = k + 1 + grp; i < N; i += ngrp) {
+                    const double* row = A + (size_t)i * N;
+                    double a0 = 0.0, a1 = 0.0;
+                    int j = k + 1 + gl;
+                    for (; j + G < N; j += 2 * G) {
+                        a0 += row[j] * vcol[j];
+                        a1 += row[j + G] * vcol[j + G];
+                    }
+                    if (j < N) a0 += row[j] * vcol[j];
+                    double acc = a0 + a1;
+                    acc += swz_xor<8>(acc);
+                    acc += swz_xor<4>(acc);
+                    acc += swz_xor<2>(acc);
+                    acc += swz_xor<1>(acc);
+                    if (gl == 0) {
+                        for (int l = 0; l < jj; ++l) acc -= Vc[l * N + i] * tvw[l] + Wc[l * N + i] * tvw[NB + l];
+                        p[i] = bet * acc;
+                        pvl += bet * acc * vcol[i];
+                    }
+                }
+                const double kk2 = bet * reduce(pvl);  // 2 kk; publishes p
+                for (int i = tid; i < N; i += nt) Wc[jj * N + i] = i > k ? p[i] - 0.5 * kk2 * vcol[i] : 0.0;
+                __syncthreads();
+            }
+            // A22 -= V W^T + W V^T over rows and columns >= k0 + nbk, a wave per row
+            const int kt = k0 + nbk;
+            for (int i = kt + wid; i < N; i += nw) {
+                double vi[NB], wi[NB];
+#pragma unroll
+                for (int l = 0; l < NB; ++l) {
+                    vi[l] = l < nbk ? Vc[l * N + i] : 0.0;
+                    wi[l] = l < nbk ? Wc[l * N + i] : 0.0;
+                }
+                double* row = A + (size_t)i * N;
+                for (int j = kt + lane; j < N; j += 64) {
+                    double a = row[j];
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) a -= vi[l] * Wc[l * N + j] + wi[l] * Vc[l * N + j];
+                    row[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    } else
     for (int k = 0; k + 2 < N; ++k) {
         double s2 = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) {
@@ -371,8 +506,10 @@ __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, 
                                                 double Jz, double beta, const KitaevBufs& b, double* red)
 {
     if (kitaev_a_in_lds(L))
-        return kitaev_weight_block_t<false>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps);
-    return kitaev_weight_block_t<true>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps);
+        return kitaev_weight_block_t<false>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps,
+                                            nullptr);
+    return kitaev_weight_block_t<true>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps,
+                                       b.vw);
 }
 
 }  // namespace crbm
