@@ -9,7 +9,8 @@
 //      doubles, 83 KiB at N = 144); for 12 < L <= 24 it no longer fits and is
 //      stored in full (N x N, row-major) in a per-chain global scratch, where
 //      every access of the reduction below is then a contiguous row;
-//   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e);
+//   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e),
+//      column by column in LDS, in panels of 8 columns when A is global;
 //   3. every eigenvalue lambda_i of the tridiagonal matrix by trisection on
 //      the Sturm count (division-free recurrence), one thread per eigenvalue;
 //   4. eps_i = sqrt(max(lambda_i, 0)); S, the fermion energy and the
@@ -151,7 +152,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     }
     __syncthreads();
 
-    // 2. Householder tridiagonalisation of the packed symmetric A.  Per step k:
+    // 2. Householder tridiagonalisation.  Packed A in LDS, unblocked, per step k:
     //    v from column k, p = bet A22 v with G = 16 lanes per row (two
     //    accumulators each, swizzle-reduced), then
     //    A22 -= v w^T + w v^T with w = p - kk v, kk = (bet/2)(p.v), i.e.
@@ -323,26 +324,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
         const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
         for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : col(i, k);
         __syncthreads();
-        // p = bet * A22 v; full form: row i of A22 is contiguous
-        if (kFull) {
-            for (int i = k + 1 + grp; i < N; i += ngrp) {
-                const double* row = A + (size_t)i * N;
-                double a0 = 0.0, a1 = 0.0;
-                int j = k + 1 + gl;
-                for (; j + G < N; j += 2 * G) {
-                    a0 += row[j] * hv[j];
-                    a1 += row[j + G] * hv[j + G];
-                }
-                if (j < N) a0 += row[j] * hv[j];
-                double acc = a0 + a1;
-                acc += swz_xor<8>(acc);
-                acc += swz_xor<4>(acc);
-                acc += swz_xor<2>(acc);
-                acc += swz_xor<1>(acc);
-                if (gl == 0) p[i] = bet * acc;
-            }
-        } else
-        // packed form, row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
+        // p = bet * A22 v; row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
         for (int i = k + 1 + grp; i < N; i += ngrp) {
             const int rb = tri(i, 0);
             double a0 = 0.0, a1 = 0.0;
@@ -369,9 +351,9 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
         double pv = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) pv += p[i] * hv[i];
         const double kk2 = bet * reduce(pv);  // 2 kk
-        // A22 -= v p^T + p v^T - 2 kk v v^T (the lower triangle, or all of it
-        // in the full form); a lane keeps the column values p_j, v_j of three
-        // columns in registers per pass, a pass per 192 columns
+        // A22 -= v p^T + p v^T - 2 kk v v^T (lower triangle); a lane keeps the
+        // column values p_j, v_j of three columns in registers per pass, a pass
+        // per 192 columns
         for (int c0 = 0; k + 1 + 64 * c0 < N; c0 += 3) {
             double pj[3], vj[3];
 #pragma unroll
@@ -381,13 +363,13 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                 vj[c] = j < N ? hv[j] : 0.0;
             }
             for (int i = k + 1 + wid; i < N; i += nw) {
-                const int rb = kFull ? i * N : tri(i, 0);
+                const int rb = tri(i, 0);
                 const double vi = hv[i], pi = p[i];
                 const double ci = pi - kk2 * vi;  // p_i - 2 kk v_i
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int j = k + 1 + lane + 64 * (c0 + c);
-                    if (kFull ? j < N : j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
+                    if (j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
                 }
             }
         }
