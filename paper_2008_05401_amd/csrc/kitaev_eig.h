@@ -11,8 +11,9 @@
 //      every access of the reduction below is then a contiguous row;
 //   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e),
 //      column by column in LDS, in panels of 8 columns when A is global;
-//   3. every eigenvalue lambda_i of the tridiagonal matrix by trisection on
-//      the Sturm count (division-free recurrence), one thread per eigenvalue;
+//   3. every eigenvalue lambda_i of the tridiagonal matrix by five-fold
+//      multisection on the Sturm count (division-free recurrence), four lanes
+//      per eigenvalue;
 //   4. eps_i = sqrt(max(lambda_i, 0)); S, the fermion energy and the
 //      fluctuation term are reduced over the workgroup.
 // Eigenvalues of A are accurate to ~N * 2^-52 * |A| in absolute terms; since
@@ -391,10 +392,9 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     for (int i = tid; i + 1 < N; i += nt) ee[i] = e[i] * e[i];
     __syncthreads();
 
-    // 3. eigenvalue idx of the tridiagonal matrix, one lane per eigenvalue, by
-    //    trisection on the Sturm count: two interior points per step give two
-    //    independent recurrences per lane (the step is latency-bound) and cut
-    //    the bracket three-fold.  The count comes from the division-free
+    // 3. eigenvalue idx of the tridiagonal matrix by multisection on the Sturm
+    //    count: a quad of lanes per eigenvalue, one interior point per lane,
+    //    the bracket cut five-fold per step.  The count comes from the division-free
     //    three-term recurrence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2},
     //    p_i = det(T_i - x), one eigenvalue below x per sign change of
     //    p_i / p_{i-1}; an exact zero is replaced by -2^-100 p_{i-1} (the sign
@@ -410,40 +410,38 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double tol = 4e-16 * scale + 1e-300;
     double S = 0.0, Ef = 0.0, Cf = 0.0;
-    for (int idx = tid; idx < N; idx += nt) {
+    // four lanes per eigenvalue (a quad), each evaluating one of four interior
+    // points: the bracket shrinks five-fold per step; the quad shares its four
+    // counts through DPP quad permutations
+    const int sub = tid & 3;
+    for (int idx = tid >> 2; idx < N; idx += nt >> 2) {
         double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
         for (int it = 0; it < 96; ++it) {
             if (!(hi - lo > tol)) break;
-            const double h = (hi - lo) * (1.0 / 3.0);
-            const double xa = lo + h, xb = hi - h;
-            if (!(xa > lo && xb < hi && xa < xb)) break;  // no representable progress
-            double pa0 = 1.0, pa1 = d[0] - xa, pb0 = 1.0, pb1 = d[0] - xb;
-            if (pa1 == 0.0) pa1 = -0x1p-100;
-            if (pb1 == 0.0) pb1 = -0x1p-100;
-            int ca = pa1 < 0.0, cb = pb1 < 0.0;
-            // one step of both recurrences
+            const double h = (hi - lo) * 0.2;
+            double xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xs[q] = lo + (double)(q + 1) * h;
+            if (!(xs[0] > lo && xs[3] < hi && xs[0] < xs[1] && xs[1] < xs[2] && xs[2] < xs[3]))
+                break;  // no representable progress
+            const double x = xs[sub];
+            double p0 = 1.0, p1 = d[0] - x;
+            if (p1 == 0.0) p1 = -0x1p-100;
+            int cnt = p1 < 0.0;
             auto step = [&](double di, double e2) {
-                double pa = fma(di - xa, pa1, -e2 * pa0);
-                double pb = fma(di - xb, pb1, -e2 * pb0);
-                if (pa == 0.0) pa = -0x1p-100 * pa1;
-                if (pb == 0.0) pb = -0x1p-100 * pb1;
-                ca += (pa < 0.0) != (pa1 < 0.0);
-                cb += (pb < 0.0) != (pb1 < 0.0);
-                pa0 = pa1;
-                pa1 = pa;
-                pb0 = pb1;
-                pb1 = pb;
+                double pn = fma(di - x, p1, -e2 * p0);
+                if (pn == 0.0) pn = -0x1p-100 * p1;
+                cnt += (pn < 0.0) != (p1 < 0.0);
+                p0 = p1;
+                p1 = pn;
             };
             auto rescale = [&]() {
-                const double fa = fabs(pa1) > 0x1p+100 ? 0x1p-100 : (fabs(pa1) < 0x1p-100 ? 0x1p+100 : 1.0);
-                const double fb = fabs(pb1) > 0x1p+100 ? 0x1p-100 : (fabs(pb1) < 0x1p-100 ? 0x1p+100 : 1.0);
-                pa0 *= fa;
-                pa1 *= fa;
-                pb0 *= fb;
-                pb1 *= fb;
+                const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                p0 *= f;
+                p1 *= f;
             };
             // the first (N - 1) % 8 steps one by one, then blocks of eight whose
-            // operands are loaded together ahead of the recurrences
+            // operands are loaded together ahead of the recurrence
             const int r0 = (N - 1) & 7;
             for (int i = 1; i <= r0; ++i) step(d[i], ee[i - 1]);
             rescale();
@@ -458,23 +456,38 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                 for (int u = 0; u < 8; ++u) step(dv[u], ev[u]);
                 rescale();
             }
+            // counts of the quad's four points (quad_perm broadcasts of lanes 0..3)
+            int c[4];
+            c[0] = __builtin_amdgcn_update_dpp(0, cnt, 0x00, 0xF, 0xF, false);
+            c[1] = __builtin_amdgcn_update_dpp(0, cnt, 0x55, 0xF, 0xF, false);
+            c[2] = __builtin_amdgcn_update_dpp(0, cnt, 0xAA, 0xF, 0xF, false);
+            c[3] = __builtin_amdgcn_update_dpp(0, cnt, 0xFF, 0xF, 0xF, false);
             // eigenvalue idx lies below x iff more than idx eigenvalues do
-            if (ca > idx) hi = xa;
-            else if (cb > idx) {
-                lo = xa;
-                hi = xb;
+            if (c[0] > idx) {
+                hi = xs[0];
+            } else if (c[1] > idx) {
+                lo = xs[0];
+                hi = xs[1];
+            } else if (c[2] > idx) {
+                lo = xs[1];
+                hi = xs[2];
+            } else if (c[3] > idx) {
+                lo = xs[2];
+                hi = xs[3];
             } else {
-                lo = xb;
+                lo = xs[3];
             }
         }
-        const double lam = 0.5 * (lo + hi);
-        const double eps = sqrt(lam > 0.0 ? lam : 0.0);
-        if (eps_out) eps_out[idx] = eps;  // may alias a packed A: it is dead after the tridiagonalisation
-        const double xv = 0.5 * beta * eps;
-        S += log2cosh_d(xv);
-        Ef -= 0.5 * eps * tanh(xv);
-        const double ch = cosh(xv);
-        Cf += (xv * xv) / (ch * ch);
+        if (sub == 0) {
+            const double lam = 0.5 * (lo + hi);
+            const double eps = sqrt(lam > 0.0 ? lam : 0.0);
+            if (eps_out) eps_out[idx] = eps;  // may alias a packed A: it is dead after the tridiagonalisation
+            const double xv = 0.5 * beta * eps;
+            S += log2cosh_d(xv);
+            Ef -= 0.5 * eps * tanh(xv);
+            const double ch = cosh(xv);
+            Cf += (xv * xv) / (ch * ch);
+        }
     }
     KitaevOut o;
     o.S = block_sum(S, red);
