@@ -450,6 +450,37 @@ def kitaev_open_boundary(periodic, L, T, n_edge=3):
     return out
 
 
+def graph_blocks(sweeps=2000, blocks=(1, 10), burnin=200):
+    return [graph_block(sweeps, b, burnin) for b in blocks]
+
+
+def graph_block(sweeps, block, burnin):
+    """The small configuration advanced in short sweep blocks (launch-bound):
+    eager launches against one HIP graph holding all the blocks; both jobs must
+    end in identical states and records."""
+    import torch
+
+    from paper_2008_05401_amd import api
+    p = api.CRBMParams.from_filters(WL_small_filters())
+    mk = lambda: api.Job(p, api.ISING, 8, np.full(64, 2.269), seed=0, burnin=burnin)  # noqa: E731
+    eager, graphed = mk(), mk()
+    g = api.SweepGraph([graphed], sweeps // block, block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(sweeps // block):
+        eager.run(block)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g.launch()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    same = bool(torch.equal(eager.state, graphed.state)) and eager.stats().tobytes() == graphed.stats().tobytes()
+    g.close()
+    return {"sweeps": sweeps, "sweeps_per_block": block, "launches": sweeps // block,
+            "eager_wall_s": t_eager, "graph_wall_s": t_graph, "identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -584,6 +615,7 @@ def main():
         out["frbm"] = frbm()
         out["analytic_per_temperature"] = analytic_per_temperature()
         out["small_config"] = small_config()
+        out["small_config_graph_blocks"] = graph_blocks()
         out["tempering"] = tempering()
         out["training"] = training_and_transfer()
         out["kitaev_training"] = kitaev_training_and_transfer()

@@ -180,6 +180,23 @@ CRBM_API crbm_status crbm_propose_accept(crbm_ctx* ctx, int32_t n_sweeps);
  * batching). All jobs must use the same stream. */
 CRBM_API crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_sweeps);
 
+/* Sweep blocks as a HIP graph: crbm_graph_create captures n_blocks >= 1
+ * launches of crbm_propose_accept_many(ctxs, n_ctx, sweeps_per_block) (same
+ * rules for the job list) into an executable graph, without running them;
+ * crbm_graph_launch enqueues the graph on the jobs' stream and counts
+ * n_blocks * sweeps_per_block sweeps for every job.  A launch does exactly
+ * what the same eager calls do (states, sums and random streams live in the
+ * jobs' device memory, not in the graph), so eager calls, tempering swaps,
+ * trace changes and graph launches may be interleaved in stream order.  The
+ * jobs must outlive the graph; the graph is bound to the tile shapes chosen
+ * when it was captured.  Host memory and one HIP graph per handle;
+ * crbm_graph_destroy releases both. */
+typedef struct crbm_graph crbm_graph;
+CRBM_API crbm_status crbm_graph_create(crbm_graph** out, crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_blocks,
+                                       int32_t sweeps_per_block);
+CRBM_API crbm_status crbm_graph_launch(crbm_graph* graph);
+CRBM_API crbm_status crbm_graph_destroy(crbm_graph* graph);
+
 /* One round of temperature swaps of parallel tempering (App. B, Eq.
  * (acceptance) between two physical temperatures), stream-ordered after the
  * job's sweeps.  The job's chains form a grid chain = rung * n_ladders +

@@ -45,6 +45,7 @@ STATS_DTYPE = np.dtype([
 assert STATS_DTYPE.itemsize == 160
 
 EXPORTS = ["crbm_workspace_size", "crbm_init", "crbm_propose_accept", "crbm_propose_accept_many",
+           "crbm_graph_create", "crbm_graph_launch", "crbm_graph_destroy",
            "crbm_tempering_swap", "crbm_set_trace", "crbm_autocorr",
            "crbm_read_stats", "crbm_sweeps_done", "crbm_destroy", "crbm_free_energy", "target_energy",
            "crbm_grad_workspace_size", "crbm_grad", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
@@ -67,6 +68,9 @@ def load(path: str = LIB_PATH):
     L.crbm_init.argtypes = [P(vp), P(crbm_params), P(crbm_batch_desc), vp]
     L.crbm_propose_accept.argtypes = [vp, ct.c_int32]
     L.crbm_propose_accept_many.argtypes = [P(vp), ct.c_int32, ct.c_int32]
+    L.crbm_graph_create.argtypes = [P(vp), P(vp), ct.c_int32, ct.c_int32, ct.c_int32]
+    L.crbm_graph_launch.argtypes = [vp]
+    L.crbm_graph_destroy.argtypes = [vp]
     L.crbm_tempering_swap.argtypes = [vp, ct.c_int32, ct.c_int32]
     L.crbm_set_trace.argtypes = [vp, vp, ct.c_int32]
     L.crbm_autocorr.argtypes = [vp, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double, vp, vp, vp, vp]
@@ -87,6 +91,7 @@ def load(path: str = LIB_PATH):
     L.crbm_last_error.restype = ct.c_char_p
     L.crbm_version.restype = ct.c_char_p
     for name in ("crbm_init", "crbm_propose_accept", "crbm_propose_accept_many", "crbm_tempering_swap",
+                 "crbm_graph_create", "crbm_graph_launch", "crbm_graph_destroy",
                  "crbm_set_trace", "crbm_autocorr",
                  "crbm_read_stats",
                  "crbm_destroy", "crbm_free_energy", "target_energy", "crbm_grad"):
@@ -118,6 +123,21 @@ def crbm_propose_accept(ctx, n_sweeps: int):
 def crbm_propose_accept_many(ctxs, n_sweeps: int):
     arr = (ct.c_void_p * len(ctxs))(*ctxs)
     check(load().crbm_propose_accept_many(arr, len(ctxs), int(n_sweeps)))
+
+
+def crbm_graph_create(ctxs, n_blocks: int, sweeps_per_block: int) -> int:
+    arr = (ct.c_void_p * len(ctxs))(*ctxs)
+    g = ct.c_void_p()
+    check(load().crbm_graph_create(ct.byref(g), arr, len(ctxs), int(n_blocks), int(sweeps_per_block)))
+    return g.value
+
+
+def crbm_graph_launch(graph):
+    check(load().crbm_graph_launch(graph))
+
+
+def crbm_graph_destroy(graph):
+    check(load().crbm_graph_destroy(graph))
 
 
 def crbm_tempering_swap(ctx, n_ladders: int, round_: int):

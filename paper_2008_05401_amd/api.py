@@ -199,6 +199,37 @@ def run_many(jobs, n_sweeps: int):
     C.crbm_propose_accept_many([j.ctx for j in jobs], int(n_sweeps))
 
 
+class SweepGraph:
+    """n_blocks blocks of sweeps_per_block sweeps of one or several jobs (same
+    stream), captured once as a HIP graph and replayed by launch(); each launch
+    advances the jobs exactly as run_many(jobs, sweeps_per_block) called
+    n_blocks times would.  Holds the jobs, which must stay open while it lives."""
+
+    def __init__(self, jobs, n_blocks: int, sweeps_per_block: int):
+        self.jobs = list(jobs)
+        self.sweeps = int(n_blocks) * int(sweeps_per_block)
+        self.graph = C.crbm_graph_create([j.ctx for j in self.jobs], int(n_blocks), int(sweeps_per_block))
+
+    def launch(self):
+        if not self.graph:
+            raise RuntimeError("graph is closed")
+        if any(j.ctx is None for j in self.jobs):
+            raise RuntimeError("a job of this graph has been closed")
+        C.crbm_graph_launch(self.graph)
+        return self
+
+    def close(self):
+        if getattr(self, "graph", None):
+            C.crbm_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autocorrelation(series: torch.Tensor, max_lag: int, c_window: float = 6.0, start: int = 0, stream=None):
     """Autocovariance C(t), t = 0..max_lag, integrated autocorrelation time and
     its automatic window for every row of `series` ([n, len] FP64 on the GPU;

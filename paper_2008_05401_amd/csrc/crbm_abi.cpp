@@ -171,9 +171,26 @@ struct crbm_ctx {
     int64_t sweeps;
 };
 
+struct crbm_graph {
+    hipGraphExec_t exec;
+    std::vector<crbm_ctx*> ctxs;
+    int64_t sweeps;  // sweeps per chain of one launch of the graph
+};
+
 namespace {
 
-crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
+crbm_status check_job_list(crbm_ctx* const* ctxs, int n_ctx)
+{
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i]) return fail(CRBM_EINVAL, "job %d is NULL", i);
+        if (ctxs[i]->stream != ctxs[0]->stream) return fail(CRBM_EINVAL, "jobs must share one stream");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(CRBM_EINVAL, "job %d listed twice", i);
+    }
+    return CRBM_OK;
+}
+
+crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode, hipStream_t s)
 {
     // group by kernel variant (and thread count / LDS) and chunk by MAX_JOBS_PER_LAUNCH
     std::vector<int> order(n);
@@ -189,7 +206,6 @@ crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode)
             return ctxs[a]->params.Lw < ctxs[b]->params.Lw;
         return false;
     });
-    hipStream_t s = ctxs[0]->stream;
     size_t i = 0;
     while (i < order.size()) {
         const crbm_ctx* c0 = ctxs[order[i]];
@@ -319,7 +335,7 @@ crbm_status crbm_propose_accept(crbm_ctx* ctx, int32_t n_sweeps)
     if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps=%d must be >= 0", n_sweeps);
     if (n_sweeps == 0) return CRBM_OK;
     crbm_ctx* one[1] = {ctx};
-    crbm_status st = launch_jobs(one, 1, n_sweeps, MODE_SWEEP);
+    crbm_status st = launch_jobs(one, 1, n_sweeps, MODE_SWEEP, ctx->stream);
     if (st == CRBM_OK) ctx->sweeps += n_sweeps;
     return st;
 }
@@ -329,16 +345,74 @@ crbm_status crbm_propose_accept_many(crbm_ctx* const* ctxs, int32_t n_ctx, int32
     if (!ctxs || n_ctx < 0) return fail(CRBM_EINVAL, "invalid job list");
     if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps=%d must be >= 0", n_sweeps);
     if (n_ctx == 0 || n_sweeps == 0) return CRBM_OK;
-    for (int i = 0; i < n_ctx; ++i) {
-        if (!ctxs[i]) return fail(CRBM_EINVAL, "job %d is NULL", i);
-        if (ctxs[i]->stream != ctxs[0]->stream) return fail(CRBM_EINVAL, "jobs must share one stream");
-        for (int j = 0; j < i; ++j)
-            if (ctxs[j] == ctxs[i]) return fail(CRBM_EINVAL, "job %d listed twice", i);
-    }
-    crbm_status st = launch_jobs(ctxs, n_ctx, n_sweeps, MODE_SWEEP);
+    crbm_status st = check_job_list(ctxs, n_ctx);
+    if (st != CRBM_OK) return st;
+    st = launch_jobs(ctxs, n_ctx, n_sweeps, MODE_SWEEP, ctxs[0]->stream);
     if (st == CRBM_OK)
         for (int i = 0; i < n_ctx; ++i) ctxs[i]->sweeps += n_sweeps;
     return st;
+}
+
+crbm_status crbm_graph_create(crbm_graph** out, crbm_ctx* const* ctxs, int32_t n_ctx, int32_t n_blocks,
+                              int32_t sweeps_per_block)
+{
+    if (!out) return fail(CRBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n_ctx < 1) return fail(CRBM_EINVAL, "a graph needs at least one job");
+    if (n_blocks < 1 || sweeps_per_block < 1)
+        return fail(CRBM_EINVAL, "n_blocks=%d and sweeps_per_block=%d must be >= 1", n_blocks, sweeps_per_block);
+    crbm_status st = check_job_list(ctxs, n_ctx);
+    if (st != CRBM_OK) return st;
+    // capture on a private stream: the jobs' stream may be the legacy default
+    // stream, which cannot be captured; the kernel nodes do not keep the stream
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    for (int b = 0; b < n_blocks && st == CRBM_OK; ++b) st = launch_jobs(ctxs, n_ctx, sweeps_per_block, MODE_SWEEP, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st != CRBM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    crbm_graph* g = new (std::nothrow) crbm_graph;
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(CRBM_EINVAL, "out of host memory");
+    }
+    g->exec = exec;
+    g->ctxs.assign(ctxs, ctxs + n_ctx);
+    g->sweeps = (int64_t)n_blocks * sweeps_per_block;
+    *out = g;
+    return CRBM_OK;
+}
+
+crbm_status crbm_graph_launch(crbm_graph* g)
+{
+    if (!g) return fail(CRBM_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, g->ctxs[0]->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    for (crbm_ctx* c : g->ctxs) c->sweeps += g->sweeps;
+    return CRBM_OK;
+}
+
+crbm_status crbm_graph_destroy(crbm_graph* g)
+{
+    if (!g) return CRBM_OK;
+    hipError_t e = hipGraphExecDestroy(g->exec);
+    delete g;
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "hipGraphExecDestroy");
 }
 
 crbm_status crbm_tempering_swap(crbm_ctx* ctx, int32_t n_ladders, int32_t round)

@@ -123,6 +123,15 @@ def test_other_entry_points_validate(lib):
     assert L.crbm_grad(ct.byref(p), 0x1000, 1, 8, 0x1000, 0x1000, 0x1000, 0x1000, None, 0, None) == _lib.CRBM_EBUDGET
     assert L.crbm_propose_accept(None, 1) == _lib.CRBM_EINVAL
     assert L.crbm_propose_accept_many(None, 1, 1) == _lib.CRBM_EINVAL
+    g = ct.c_void_p(0x1000)
+    assert L.crbm_graph_create(ct.byref(g), None, 1, 1, 1) == _lib.CRBM_EINVAL and g.value is None
+    assert L.crbm_graph_create(None, None, 1, 1, 1) == _lib.CRBM_EINVAL
+    jobs = (ct.c_void_p * 1)(None)
+    assert L.crbm_graph_create(ct.byref(g), jobs, 0, 1, 1) == _lib.CRBM_EINVAL        # no job
+    assert L.crbm_graph_create(ct.byref(g), jobs, 1, 1, 1) == _lib.CRBM_EINVAL        # NULL job
+    assert L.crbm_graph_create(ct.byref(g), jobs, 1, 0, 1) == _lib.CRBM_EINVAL        # no block
+    assert L.crbm_graph_launch(None) == _lib.CRBM_EINVAL
+    assert L.crbm_graph_destroy(None) == _lib.CRBM_OK
     assert L.crbm_tempering_swap(None, 1, 0) == _lib.CRBM_EINVAL
     assert L.crbm_set_trace(None, 0x1000, 4) == _lib.CRBM_EINVAL
     ac = L.crbm_autocorr
