@@ -40,14 +40,14 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 # after any change to them `traffic` is reported as null until re-measured.
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising.hip", "paper_2008_05401_amd/csrc/device_common.h",
                   "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": "6358d54c730092f6f50c87e911db31ac3f71fea178718b92d0d60033a467f5b8",
+MEASURED_TRAFFIC = {"sources_sha256": "017da39dd54bb2c7510ca3224437dfcb53e3c308eb252cad8f5fab480f691b5d",
                     "chains": 4096, "L": 64, "sweeps_per_launch": 100,
-                    "fetch_kib": 9768.0, "fetch_scale": 2.0, "write_kib": 24295.3, "write_scale": 1.0}
+                    "fetch_kib": 9773.6, "fetch_scale": 2.0, "write_kib": 24284.1, "write_scale": 1.0}
 
 # VALU issue of the same kernel from SQ counters (rocprofv3 --pmc SQ_INSTS_VALU ... GRBM_GUI_ACTIVE),
 # reported while the kernel sources hash to the measured ones
-MEASURED_VALU = {"sources_sha256": "6358d54c730092f6f50c87e911db31ac3f71fea178718b92d0d60033a467f5b8",
-                 "valu_wave_instr_per_site_sweep": 7.755, "valu_issue_fraction": 1.09,
+MEASURED_VALU = {"sources_sha256": "017da39dd54bb2c7510ca3224437dfcb53e3c308eb252cad8f5fab480f691b5d",
+                 "valu_wave_instr_per_site_sweep": 7.755, "valu_issue_fraction": 1.08,
                  "lds_bank_conflicts_per_access": 8.9e-04}
 
 
@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--served-warmup", type=float, default=5.0)
     ap.add_argument("--served-sweeps", type=int, default=20)
     ap.add_argument("--plain-jobs", type=int, default=5)
+    ap.add_argument("--only-kitaev", action="store_true",
+                    help="run only the Kitaev sweep measurements (for profiling) and print them")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (scale for HBM counters)")
     args = ap.parse_args()
@@ -511,6 +513,9 @@ def main():
     from paper_2008_05401_amd import api, workloads as WL
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_kitaev:
+        print(json.dumps({"kitaev": kitaev()}), flush=True)
+        return
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -320,7 +320,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
         delete c;
         return fail(CRBM_EUNSUPPORTED, "initialisation needs %zu bytes of LDS", lds);
     }
-    e = launch_init(P, desc->n_chains, lds, c->stream);
+    e = launch_init(P, desc->n_chains, lds, desc->target == CRBM_KITAEV && pl.nt > 256 ? pl.nt : 256, c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init launch");

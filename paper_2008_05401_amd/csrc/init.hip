@@ -21,7 +21,8 @@ __host__ __device__ inline size_t init_lds_bytes(int K, int C, int LW, int L, in
     return o;
 }
 
-__global__ __launch_bounds__(256) void init_kernel(SweepLaunch P)
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void init_kernel(SweepLaunch P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     int jb = 0;
@@ -99,9 +100,13 @@ size_t init_lds(int K, int C, int LW, int L, int target, int banks, int dense)
     return init_lds_bytes(K, C, LW, L, target, banks, dense);
 }
 
-hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s)
+hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s)
 {
-    hipLaunchKernelGGL(init_kernel, dim3(n_blocks), dim3(256), lds, s, P);
+    // the Kitaev eigen-step runs with the thread count of the job's sweeps
+    if (nt == 1024)
+        hipLaunchKernelGGL(init_kernel<1024>, dim3(n_blocks), dim3(1024), lds, s, P);
+    else
+        hipLaunchKernelGGL(init_kernel<256>, dim3(n_blocks), dim3(256), lds, s, P);
     return hipGetLastError();
 }
 

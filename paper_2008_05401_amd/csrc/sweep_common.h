@@ -55,7 +55,7 @@ hipError_t launch_autocorr(const double* trace, int n, int len, int start, int m
 hipError_t launch_tempering_swap(const JobDev* job_dev, int n_pairs, int n_ladders, int q0, uint32_t round,
                                  int target, hipStream_t s);
 size_t init_lds(int K, int C, int LW, int L, int target, int banks, int dense);
-hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, hipStream_t s);
+hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);
 hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt, hipStream_t s);
 
 }  // namespace crbm
