@@ -80,6 +80,8 @@ def test_graph_mixed_jobs_with_trace(api):
         return [api.Job(api.CRBMParams.from_filters(fa), api.ISING, 8, np.full(5, 2.2), seed=1),
                 api.Job(api.CRBMParams.from_filters(fb), api.ISING, 16, np.full(7, 2.5), seed=2, chain_offset=40),
                 api.Job(api.CRBMParams.from_filters(fk), api.KITAEV, 4, np.full(3, 0.05), seed=3),
+                # beyond L = 12 the eigen-step works in the job's global scratch
+                api.Job(api.CRBMParams.from_filters(fk), api.KITAEV, 13, np.full(2, 0.1), seed=6),
                 api.Job(api.CRBMParams.from_filters(ff, dense=True), api.ISING, 8, np.full(4, 2.0), seed=5,
                         boundary=1)]
     eager, graphed = mk(), mk()
