@@ -105,6 +105,8 @@ hipError_t launch_init(const SweepLaunch& P, int n_blocks, size_t lds, int nt, h
     // the Kitaev eigen-step runs with the thread count of the job's sweeps
     if (nt == 1024)
         hipLaunchKernelGGL(init_kernel<1024>, dim3(n_blocks), dim3(1024), lds, s, P);
+    else if (nt == 512)
+        hipLaunchKernelGGL(init_kernel<512>, dim3(n_blocks), dim3(512), lds, s, P);
     else
         hipLaunchKernelGGL(init_kernel<256>, dim3(n_blocks), dim3(256), lds, s, P);
     return hipGetLastError();

@@ -305,6 +305,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 }
 
 template __global__ void sweep_generic_kernel<1024>(SweepLaunch);
+template __global__ void sweep_generic_kernel<512>(SweepLaunch);
 template __global__ void sweep_generic_kernel<256>(SweepLaunch);
 template __global__ void sweep_generic_kernel<64>(SweepLaunch);
 
@@ -323,6 +324,8 @@ hipError_t launch_generic(const SweepLaunch& P, int n_blocks, size_t lds, int nt
         hipLaunchKernelGGL(sweep_generic_kernel<64>, dim3(n_blocks), dim3(64), lds, s, P);
     } else if (nt == 1024) {
         hipLaunchKernelGGL(sweep_generic_kernel<1024>, dim3(n_blocks), dim3(1024), lds, s, P);
+    } else if (nt == 512) {
+        hipLaunchKernelGGL(sweep_generic_kernel<512>, dim3(n_blocks), dim3(512), lds, s, P);
     } else {
         hipLaunchKernelGGL(sweep_generic_kernel<256>, dim3(n_blocks), dim3(256), lds, s, P);
     }
