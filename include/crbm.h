@@ -160,7 +160,9 @@ typedef struct {
 typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
 
 /* Bytes of device workspace a job needs (per-chain records plus internal
- * buffers).  Returns 0 for invalid arguments. Host only, no device work.
+ * buffers: the bit-packed Ising kernel's filter tables, the Kitaev singular
+ * values and eigen-step scratch).  Returns 0 for invalid arguments. Host
+ * only, no device work.
  * Kitaev jobs run up to L = 24: up to L = 12 the eigen-step keeps M^T M in
  * LDS; beyond, the workspace also holds an N x N FP64 matrix per chain
  * (N = L^2; 2.7 MB per chain at L = 24). */
@@ -169,6 +171,11 @@ CRBM_API size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_
 /* Create a job handle: copies `params`/`desc` (the pointed-to device buffers
  * must stay valid until crbm_destroy), optionally fills the initial state,
  * computes F and the target of every chain's state and zeroes the sums.
+ * For jobs on the bit-packed Ising kernel (C = 1, periodic, L a power of two
+ * from 8 to 256, Lw <= 6) it also builds, once, the kernel's tables of the
+ * filters (subset sums of every filter row, error bands) in the workspace:
+ * the filters and biases are therefore read at crbm_init and must not change
+ * while the job lives (create a new job for new parameters).
  * Sweep numbering starts at 0. Asynchronous on `stream`. */
 CRBM_API crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batch_desc* desc, void* stream);
 

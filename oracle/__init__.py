@@ -93,6 +93,7 @@ def lib():
         L.orc_pt_uniform.restype = ct.c_double
         L.orc_grad.argtypes = [P(_Params), vp, ct.c_int, ct.c_int, vp, vp, vp, vp]
         L.orc_num_threads.restype = ct.c_int
+        L.orc_set_threads.argtypes = [ct.c_int]
         _lib = L
     return _lib
 
@@ -345,3 +346,8 @@ class Chains:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops over chains (timing of the CPU baseline)."""
+    lib().orc_set_threads(int(n))

@@ -763,3 +763,13 @@ ORC_API int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Harness only (timing of the CPU baseline): threads of the OpenMP loops over chains. */
+ORC_API void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}

@@ -9,7 +9,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrbm.so")
-SOURCES = ["crbm_abi.cpp", "init.hip", "sweep_generic.hip", "sweep_ising.hip", "ops.hip", "tempering.hip", "autocorr.hip"]
+SOURCES = ["crbm_abi.cpp", "init.hip", "sweep_generic.hip", "sweep_ising.hip", "ops.hip", "tempering.hip", "autocorr.hip",
+           # the bit-packed Ising kernel, one unit per compiled (K, Lw) pair so that they build in parallel
+           "sweep_ising_k8l5.hip", "sweep_ising_k8l3.hip", "sweep_ising_k4l3.hip", "sweep_ising_k2l2.hip",
+           "sweep_ising_kxl1.hip", "sweep_ising_kxl2.hip", "sweep_ising_kxl3.hip", "sweep_ising_kxl4.hip",
+           "sweep_ising_kxl5.hip", "sweep_ising_kxl6.hip"]
 ARCH = os.environ.get("CRBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -28,7 +32,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source to an object in _build/ and link libcrbm.so in-tree."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)

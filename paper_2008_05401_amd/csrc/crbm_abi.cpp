@@ -142,6 +142,7 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // workspace: [job descriptor][one record per chain][Kitaev: singular values, n_chains x L^2 doubles]
 //            [Kitaev beyond L = 12: eigen-step scratch, n_chains x kitaev_scratch_bytes(L)]
+//            [bit-packed Ising kernel: table block of the filters, ising_tab_bytes(K, Lw)]
 size_t records_end(int n_chains) { return round_up(kJobBytes + (size_t)n_chains * sizeof(ChainRec), 256); }
 
 size_t eps_end(const crbm_batch_desc* d)
@@ -151,10 +152,18 @@ size_t eps_end(const crbm_batch_desc* d)
     return o;
 }
 
-size_t workspace_bytes_for(const crbm_batch_desc* d)
+size_t scratch_end(const crbm_batch_desc* d)
 {
     size_t o = eps_end(d);
     if (d->target == CRBM_KITAEV) o += round_up((size_t)d->n_chains * kitaev_scratch_bytes(d->L), 256);
+    return o;
+}
+
+// [... Kitaev regions][bit-packed Ising kernel: the job's table block]
+size_t workspace_bytes_for(const crbm_params* p, const crbm_batch_desc* d, const Plan& pl)
+{
+    size_t o = scratch_end(d);
+    if (pl.kernel == K_ISING_FAST) o += round_up(ising_tab_bytes(p->K, p->Lw), 256);
     return o;
 }
 
@@ -247,7 +256,7 @@ size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* des
 {
     Plan pl;
     if (plan_job(params, desc, &pl) != CRBM_OK) return 0;
-    return workspace_bytes_for(desc);
+    return workspace_bytes_for(params, desc, pl);
 }
 
 crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batch_desc* desc, void* stream)
@@ -258,7 +267,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     crbm_status st = plan_job(params, desc, &pl);
     if (st != CRBM_OK) return st;
     if (!desc->T || !desc->state || !desc->workspace) return fail(CRBM_EINVAL, "T, state and workspace must be device pointers");
-    const size_t need = workspace_bytes_for(desc);
+    const size_t need = workspace_bytes_for(params, desc, pl);
     if (desc->workspace_bytes < need)
         return fail(CRBM_EBUDGET, "workspace of %zu bytes, %zu needed", desc->workspace_bytes, need);
     if (((uintptr_t)desc->workspace & 255) != 0) return fail(CRBM_EINVAL, "workspace must be 256-byte aligned");
@@ -284,6 +293,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.kitA = (desc->target == CRBM_KITAEV && kitaev_scratch_bytes(desc->L) > 0)
                  ? (double*)((char*)desc->workspace + eps_end(desc))
                  : nullptr;
+    j.tab = pl.kernel == K_ISING_FAST ? (unsigned char*)desc->workspace + scratch_end(desc) : nullptr;
     j.J0 = desc->J[0];
     j.J1 = desc->J[1];
     j.J2 = desc->J[2];
@@ -306,6 +316,14 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "hipMemcpyAsync(job)");
+    }
+    if (pl.kernel == K_ISING_FAST) {
+        // the bit-packed kernel's tables depend on the filters only: built once here
+        e = launch_ising_tables(c->job_dev, c->stream);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "table launch");
+        }
     }
     SweepLaunch P;
     memset(&P, 0, sizeof P);

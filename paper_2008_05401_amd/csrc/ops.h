@@ -16,6 +16,8 @@ size_t kitaev_weight_lds(int C, int L);
 hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_cols, double Jx, double Jy, double Jz,
                                 const double* T, double* S, hipStream_t s);
 size_t grad_lds(int K, int C, int LW, int L, int banks);
+// 1: grad_stage1 keeps sigma of the hidden units in FP64 (else float32)
+bool grad_sig64(int K, int C, int LW, int L, int banks);
 // fully connected RBM: W[K][nv], hbias[K], vbias[nv], nv = C L^2
 size_t free_energy_dense_lds(int nv);
 hipError_t launch_free_energy_dense(const float* W, const float* hb, const float* vb, int K, int nv, const int8_t* x,

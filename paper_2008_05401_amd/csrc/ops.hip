@@ -181,22 +181,23 @@ hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_c
 
 // ---------------------------------------------------------------------------
 // Backward of F.  Stage 1 (one workgroup per sample b): sigma(a) of every
-// hidden unit (float32 pre-activation, FP64 sigmoid, stored as float), then one
-// thread per parameter p forms g_b dF(x_b)/dtheta_p in FP64 into
-// part[b][p].  Stage 2: out[p] = sum_b part[b][p] in sample order.
+// hidden unit from its FP64 pre-activation, kept in LDS as FP64 (as float32
+// when K L^2 doubles do not fit, `sig64` = 0), then one thread per parameter p
+// forms g_b dF(x_b)/dtheta_p in FP64 into part[b][p].  Stage 2: out[p] =
+// sum_b part[b][p] in sample order, rounded once to float32.
 // Parameters are ordered W[banks][K][C][LW][LW], hbias[banks][K], vbias[C];
 // a bank's gradient sums over the hidden columns that bank owns.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, const float* __restrict__ hb, int K,
-                                                   int C, int LW, int open, int ne, const int8_t* __restrict__ x,
-                                                   int L, const float* __restrict__ gF, double* __restrict__ part)
+template <typename SigT>
+__device__ void grad_stage1_body(const float* __restrict__ W, const float* __restrict__ hb, int K, int C, int LW,
+                                 int open, int ne, const int8_t* __restrict__ x, int L, const float* __restrict__ gF,
+                                 double* __restrict__ part, unsigned char* smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int nb = 1 + 2 * ne;
     const int LL = L * L, nW = K * C * LW * LW, P = nb * (nW + K) + C;
-    float* Ws = (float*)smem;
-    float* sg = Ws + nb * nW;
-    uint8_t* v = (uint8_t*)(sg + K * LL);
+    SigT* sg = (SigT*)smem;
+    float* Ws = (float*)(sg + K * LL);
+    uint8_t* v = (uint8_t*)(Ws + nb * nW);
     const int8_t* xs = x + (size_t)blockIdx.x * C * LL;
     for (int q = threadIdx.x; q < nb * nW; q += blockDim.x) Ws[q] = W[q];
     for (int q = threadIdx.x; q < C * LL; q += blockDim.x) v[q] = xs[q] > 0;
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
         const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
         const int bk = bank_of_col(j, L, ne);
         const int taps = open ? min(LW, L - j) : LW;
-        float acc = hb[bk * K + k];
+        double acc = (double)hb[bk * K + k];
         for (int c = 0; c < C; ++c)
             for (int a = 0; a < LW; ++a) {
                 int ia = i + a;
@@ -215,10 +216,10 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
                 for (int b = 0; b < taps; ++b) {
                     int jb = j + b;
                     if (jb >= L) jb -= L;
-                    acc = fmaf(wr[b], (float)row[jb], acc);
+                    if (row[jb]) acc += (double)wr[b];
                 }
             }
-        sg[q] = (float)(1.0 / (1.0 + exp(-(double)acc)));
+        sg[q] = (SigT)(1.0 / (1.0 + exp(-acc)));
     }
     __syncthreads();
     const double gb = (double)gF[blockIdx.x];
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
         if (p < nb * nW) {
             const int bank = p / nW, pw = p - bank * nW;
             const int b = pw % LW, a = (pw / LW) % LW, c = (pw / (LW * LW)) % C, k = pw / (C * LW * LW);
-            const float* sk = sg + k * LL;
+            const SigT* sk = sg + k * LL;
             // hidden columns of this bank whose tap b stays inside the lattice
             int j0, j1;
             bank_columns(bank, L, ne, j0, j1);
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
                 int ia = i + a;
                 if (ia >= L) ia -= L;
                 const uint8_t* row = v + (c * L + ia) * L;
-                const float* srow = sk + i * L;
+                const SigT* srow = sk + i * L;
                 for (int j = j0; j < j1; ++j) {
                     int jb = j + b;
                     if (jb >= L) jb -= L;
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
             }
         } else if (p < nb * (nW + K)) {
             const int q0 = p - nb * nW, bank = q0 / K, k = q0 - bank * K;
-            const float* sk = sg + k * LL;
+            const SigT* sk = sg + k * LL;
             int j0, j1;
             bank_columns(bank, L, ne, j0, j1);
             for (int i = 0; i < L; ++i)
@@ -257,6 +258,18 @@ __global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, 
         }
         out[p] = -gb * s;
     }
+}
+
+__global__ __launch_bounds__(256) void grad_stage1(const float* __restrict__ W, const float* __restrict__ hb, int K,
+                                                   int C, int LW, int open, int ne, const int8_t* __restrict__ x,
+                                                   int L, const float* __restrict__ gF, double* __restrict__ part,
+                                                   int sig64)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (sig64)
+        grad_stage1_body<double>(W, hb, K, C, LW, open, ne, x, L, gF, part, smem);
+    else
+        grad_stage1_body<float>(W, hb, K, C, LW, open, ne, x, L, gF, part, smem);
 }
 
 __global__ __launch_bounds__(256) void grad_stage2(const double* __restrict__ part, int B, int P, int nW, int K,
@@ -274,37 +287,39 @@ __global__ __launch_bounds__(256) void grad_stage2(const double* __restrict__ pa
 
 // Backward of the fully connected RBM's F: parameters W[K][nv], hbias[K],
 // vbias[nv]; dF/dW[k][q] = -sigma(a_k) v_q, dF/dhb[k] = -sigma(a_k),
-// dF/dvb[q] = -v_q.  Stage 1 per sample as above, stage 2 shared.
+// dF/dvb[q] = -v_q.  Stage 1 per sample as above (FP64 pre-activations and
+// sigma), stage 2 shared.
 __global__ __launch_bounds__(256) void grad_dense_stage1(const float* __restrict__ W, const float* __restrict__ hb,
                                                          int K, int nv, const int8_t* __restrict__ x,
                                                          const float* __restrict__ gF, double* __restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int P = K * nv + K + nv;
-    float* sg = (float*)smem;
+    double* sg = (double*)smem;
     uint8_t* v = (uint8_t*)(sg + K);
     const int8_t* xs = x + (size_t)blockIdx.x * nv;
     for (int q = threadIdx.x; q < nv; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const float* w = W + (size_t)k * nv;
-        float acc = hb[k];
-        for (int q = 0; q < nv; ++q) acc = fmaf(w[q], (float)v[q], acc);
-        sg[k] = (float)(1.0 / (1.0 + exp(-(double)acc)));
+        double acc = (double)hb[k];
+        for (int q = 0; q < nv; ++q)
+            if (v[q]) acc += (double)w[q];
+        sg[k] = 1.0 / (1.0 + exp(-acc));
     }
     __syncthreads();
     const double gb = (double)gF[blockIdx.x];
     double* out = part + (size_t)blockIdx.x * P;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         double s;
-        if (p < K * nv) s = v[p % nv] ? (double)sg[p / nv] : 0.0;
-        else if (p < K * nv + K) s = (double)sg[p - K * nv];
+        if (p < K * nv) s = v[p % nv] ? sg[p / nv] : 0.0;
+        else if (p < K * nv + K) s = sg[p - K * nv];
         else s = (double)v[p - K * nv - K];
         out[p] = -gb * s;
     }
 }
 
-size_t grad_dense_lds(int K, int nv) { return (size_t)K * 4 + (size_t)nv + 16; }
+size_t grad_dense_lds(int K, int nv) { return (size_t)K * 8 + (size_t)nv + 16; }
 
 hipError_t launch_grad_dense(const float* W, const float* hb, int K, int nv, const int8_t* x, int B, const float* gF,
                              double* part, float* dW, float* dhb, float* dvb, hipStream_t s)
@@ -319,9 +334,18 @@ hipError_t launch_grad_dense(const float* W, const float* hb, int K, int nv, con
     return hipGetLastError();
 }
 
+// LDS of grad_stage1: sigma of every hidden unit (FP64, or float32 when that
+// does not fit 160 KiB), the filters, the sample's visible units
+size_t grad_lds_sig(int K, int C, int LW, int L, int banks, int sig_bytes)
+{
+    return (size_t)K * L * L * sig_bytes + (size_t)banks * (K * C * LW * LW) * 4 + (size_t)C * L * L + 16;
+}
+
+bool grad_sig64(int K, int C, int LW, int L, int banks) { return grad_lds_sig(K, C, LW, L, banks, 8) <= 160 * 1024; }
+
 size_t grad_lds(int K, int C, int LW, int L, int banks)
 {
-    return (size_t)banks * (K * C * LW * LW) * 4 + (size_t)K * L * L * 4 + (size_t)C * L * L + 16;
+    return grad_lds_sig(K, C, LW, L, banks, grad_sig64(K, C, LW, L, banks) ? 8 : 4);
 }
 
 hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, int open, int ne, const int8_t* x, int B,
@@ -331,7 +355,7 @@ hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, in
     const int P = nb * (K * C * LW * LW + K) + C;
     if (B > 0) {
         hipLaunchKernelGGL(grad_stage1, dim3(B), dim3(256), grad_lds(K, C, LW, L, nb), s, W, hb, K, C, LW, open, ne, x,
-                           L, gF, part);
+                           L, gF, part, grad_sig64(K, C, LW, L, nb) ? 1 : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

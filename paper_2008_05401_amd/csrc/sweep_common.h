@@ -20,6 +20,7 @@ struct JobDev {
     double* eps;        // Kitaev: singular values of every chain's current state [n_chains][L*L]
     double* trace;      // per-sweep energy ring buffer [n_chains][trace_len] or nullptr
     double* kitA;       // Kitaev beyond L = 12: per-chain global scratch of the eigen-step
+    unsigned char* tab; // bit-packed Ising kernel: the job's table block (built at crbm_init)
     double J0, J1, J2;
     uint64_t seed;
     int K, C, LW, target, L, n_chains, gibbs_k, burnin;

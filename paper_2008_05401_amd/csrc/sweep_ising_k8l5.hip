@@ -1,0 +1,3 @@
+// sweep_ising_k8l5.hip -- bit-packed Ising sweep kernels for K = 8, Lw = 5.
+#include "sweep_ising_launch.h"
+CRBM_ISING_INSTANTIATE(8, 5)

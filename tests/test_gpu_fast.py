@@ -101,6 +101,43 @@ def test_batched_config_sampled_chains(orc, api):
             assert st[name][g] == ch.rec[name][0]
 
 
+def test_timed_launch_parity(orc, api):
+    # the launch bench.py times: 4096 chains, L=64, K=8 5x5 filters ~ N(0, 0.05) (seed 0),
+    # 32 temperatures, tuned tile shape, burn-in = warm-up + steps // 10 (driver: 5 + 2);
+    # 5 warm-up sweeps, one 100-sweep launch (it crosses the 64-sweep refill of the MH
+    # uniforms) and one 20-sweep launch.  Two chains of every temperature block
+    # (g = 128 t and 128 t + 127) are recomputed one by one by the oracle.
+    from concurrent.futures import ThreadPoolExecutor
+    L, n, burnin = 64, 4096, 7
+    f = WL.random_filters(8, 1, 5, 0.05, seed=0)
+    T = WL.ising_temperatures_linspace(32, 1.5, 3.5, n)
+    job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=0, burnin=burnin)
+    blocks = (5, 100, 20)
+    for b in blocks:
+        job.run(b)
+    st = job.stats()
+    state = job.state.cpu().numpy()
+    m = orc.CRBM(f.W, f.hbias, f.vbias)
+    picks = [g for t in range(32) for g in (128 * t, 128 * t + 127)]
+
+    def one(g):
+        ch = orc.Chains(m, orc.ISING, L, T[g:g + 1], seed=0, burnin=burnin, g0=g)
+        for b in blocks:
+            ch.run(b)
+        return g, ch
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        done = list(ex.map(one, picks))
+    for g, ch in done:
+        assert np.array_equal(state[g], ch.state[0]), g
+        for name in ("sweeps", "n_acc", "n_meas", "E", "sumE", "sumE2", "sumM", "sumAbsM", "sumM2"):
+            assert st[name][g] == ch.rec[name][0], (g, name)
+        assert abs(st["F"][g] - ch.rec["F"][0]) <= st["F_bound"][g] + 1e-9 + 1e-11 * abs(ch.rec["F"][0]), g
+        assert ch.ties[0] == 0 and ch.ties[1] == 0, g
+    # the first sweeps out of the random start accept some proposals
+    assert st["n_acc"][picks].sum() > 0
+
+
 def test_resume_is_bitwise(api):
     f = WL.random_filters(8, 1, 5, 0.05, seed=1)
     T = np.linspace(1.5, 3.5, 32)

@@ -2,7 +2,8 @@
 the same seeded inputs.
 
 Bars (stated per test): integer energies, states and accept decisions are
-bit-exact; floating-point values agree to 1e-5 relative or better.  The
+bit-exact; floating-point values agree to 1e-5 relative or better; gradients
+per element within the bar of tests/grad_bar.py.  The
 oracle's tie counters must be zero for bitwise comparisons to be meaningful
 (a decision within 1e-6 of its threshold may legitimately differ).
 """
@@ -18,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+from grad_bar import R_SIG32, R_SIG64, assert_grad_close, grad_abs, sigma_is_fp64  # noqa: E402
 from paper_2008_05401_amd import workloads as WL  # noqa: E402
 
 
@@ -91,12 +93,28 @@ def test_grad_parity(orc, api, K, C, Lw, L, B):
     f = WL.random_filters_with_bias(K, C, Lw, 0.2, 0.3, seed=1)
     x = WL.random_states(B, C, L, seed=2)
     g = np.random.default_rng(3).standard_normal(B).astype(np.float32)
-    dWo, dhbo, dvbo = orc.grad(_o_crbm(orc, f), x, g.astype(np.float64))
+    m = _o_crbm(orc, f)
+    dWo, dhbo, dvbo = orc.grad(m, x, g.astype(np.float64))
     dWg, dhbg, dvbg = api.grad(_p(api, f), torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda())
-    for got, ref in ((dWg, dWo), (dhbg, dhbo), (dvbg, dvbo)):
-        got = got.cpu().numpy().astype(np.float64)
-        scale = np.abs(ref).max() + 1e-30
-        assert np.abs(got - ref).max() <= 1e-5 * scale
+    A = grad_abs(orc, m, x, g)
+    r = R_SIG64 if sigma_is_fp64(K, C, Lw, L) else R_SIG32
+    for got, ref, a in zip((dWg, dhbg, dvbg), (dWo, dhbo, dvbo), A):
+        assert_grad_close(got.cpu().numpy(), ref, a, r)
+
+
+def test_grad_parity_float32_sigma(orc, api):
+    # K L^2 doubles beyond LDS (K=8, L=64): sigma is kept as float32
+    K, C, Lw, L, B = 8, 1, 5, 64, 24
+    assert not sigma_is_fp64(K, C, Lw, L)
+    f = WL.random_filters_with_bias(K, C, Lw, 0.2, 0.3, seed=4)
+    x = WL.random_states(B, C, L, seed=5)
+    g = np.random.default_rng(6).standard_normal(B).astype(np.float32)
+    m = _o_crbm(orc, f)
+    ref = orc.grad(m, x, g.astype(np.float64))
+    got = api.grad(_p(api, f), torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda())
+    A = grad_abs(orc, m, x, g)
+    for a, rr, aa in zip(got, ref, A):
+        assert_grad_close(a.cpu().numpy(), rr, aa, R_SIG32)
 
 
 def test_grad_empty_batch(api):
