@@ -287,6 +287,21 @@ CRBM_API crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32
                       float* dW, float* dhbias, float* dvbias, void* workspace, size_t workspace_bytes,
                       void* stream);
 
+/* crbm_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, arguments and results as crbm_grad, with the per-sample
+ * partial gradients in a static scratch of 8 MiB that the library holds on
+ * every GPU it runs on until the process ends, instead of a caller
+ * workspace.  The call allocates nothing; it needs crbm_grad_workspace_size
+ * (params, B) <= 8 MiB (B * P * 8 bytes, P = banks (K C Lw^2 + K) + C, or
+ * K C L^2 + K + C L^2 for a dense RBM: B <= 5017 for K = 8, Lw = 5) and
+ * returns CRBM_EBUDGET beyond that, without launching.  Calls on one GPU share
+ * the scratch: calls that overlap on one GPU (several streams, several host
+ * threads) race; serialise them.  The device current at the call must be the
+ * one the pointers and the stream belong to. */
+CRBM_API crbm_status crbm_grad_static(const crbm_params* params, const int8_t* x, int32_t B, int32_t L,
+                                      const float* gF, float* dW, float* dhbias, float* dvbias, void* stream);
+
 /* Tile choice of the bit-packed Ising sweep for jobs with this (L, K, Lw):
  * `rows` lattice rows x 4 columns per lane (1, 2 or 4) and `threads` per
  * workgroup (64, 256, 512 or 1024).  Process-wide; applies to jobs created after the

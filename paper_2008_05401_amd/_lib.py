@@ -48,7 +48,7 @@ EXPORTS = ["crbm_workspace_size", "crbm_init", "crbm_propose_accept", "crbm_prop
            "crbm_graph_create", "crbm_graph_launch", "crbm_graph_destroy",
            "crbm_tempering_swap", "crbm_set_trace", "crbm_autocorr",
            "crbm_read_stats", "crbm_sweeps_done", "crbm_destroy", "crbm_free_energy", "target_energy",
-           "crbm_grad_workspace_size", "crbm_grad", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
+           "crbm_grad_workspace_size", "crbm_grad", "crbm_grad_static", "crbm_set_tuning", "crbm_clear_tuning", "crbm_last_error",
            "crbm_version"]
 
 _lib = None
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.crbm_grad_workspace_size.argtypes = [P(crbm_params), ct.c_int32]
     L.crbm_grad_workspace_size.restype = ct.c_size_t
     L.crbm_grad.argtypes = [P(crbm_params), vp, ct.c_int32, ct.c_int32, vp, vp, vp, vp, vp, ct.c_size_t, vp]
+    L.crbm_grad_static.argtypes = [P(crbm_params), vp, ct.c_int32, ct.c_int32, vp, vp, vp, vp, vp]
     L.crbm_set_tuning.argtypes = [ct.c_int32] * 5
     L.crbm_set_tuning.restype = ct.c_int
     L.crbm_clear_tuning.argtypes = []
@@ -94,7 +95,7 @@ def load(path: str = LIB_PATH):
                  "crbm_graph_create", "crbm_graph_launch", "crbm_graph_destroy",
                  "crbm_set_trace", "crbm_autocorr",
                  "crbm_read_stats",
-                 "crbm_destroy", "crbm_free_energy", "target_energy", "crbm_grad"):
+                 "crbm_destroy", "crbm_free_energy", "target_energy", "crbm_grad", "crbm_grad_static"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -181,6 +182,10 @@ def crbm_grad_workspace_size(params, B) -> int:
 
 def crbm_grad(params, x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, ws_ptr, ws_bytes, stream):
     check(load().crbm_grad(ct.byref(params), x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, ws_ptr, ws_bytes, stream))
+
+
+def crbm_grad_static(params, x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, stream):
+    check(load().crbm_grad_static(ct.byref(params), x_ptr, B, L, gF_ptr, dW_ptr, dhb_ptr, dvb_ptr, stream))
 
 
 def crbm_set_tuning(L, K, Lw, rows, threads):

@@ -289,6 +289,21 @@ def grad(params: CRBMParams, x: torch.Tensor, gF: torch.Tensor, stream=None):
     return dW, dhb, dvb
 
 
+def grad_static(params: CRBMParams, x: torch.Tensor, gF: torch.Tensor, stream=None):
+    """As grad(), through crbm_grad_static: no workspace, the library's static
+    scratch (at most 8 MiB of partial gradients; calls on one GPU must not
+    overlap).  The outputs are the caller's tensors, allocated here."""
+    x = x.to(device=params.W.device, dtype=torch.int8).contiguous()
+    B, L = int(x.shape[0]), int(x.shape[-1])
+    g = gF.to(device=x.device, dtype=torch.float32).contiguous().reshape(B)
+    dW = torch.empty_like(params.W)
+    dhb = torch.empty_like(params.hbias)
+    dvb = torch.empty_like(params.vbias)
+    C.crbm_grad_static(params.struct(), x.data_ptr(), B, L, g.data_ptr(), dW.data_ptr(), dhb.data_ptr(),
+                       dvb.data_ptr(), _stream_ptr(stream))
+    return dW, dhb, dvb
+
+
 class CRBMFreeEnergy(torch.autograd.Function):
     """F(x; W, hbias, vbias) with the hand-written backward kernel.
 

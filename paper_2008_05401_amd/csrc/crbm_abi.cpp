@@ -557,6 +557,25 @@ size_t crbm_grad_workspace_size(const crbm_params* params, int32_t B)
     return round_up(std::max<size_t>(1, (size_t)B) * P * sizeof(double), 256);
 }
 
+crbm_status crbm_grad_static(const crbm_params* params, const int8_t* x, int32_t B, int32_t L, const float* gF,
+                             float* dW, float* dhbias, float* dvbias, void* stream)
+{
+    crbm_status st = check_params(params);
+    if (st != CRBM_OK) return st;
+    if (B < 0) return fail(CRBM_EINVAL, "B=%d must be >= 0", B);
+    const size_t need = crbm_grad_workspace_size(params, B);
+    if (need > GRAD_STATIC_BYTES)
+        return fail(CRBM_EBUDGET, "crbm_grad_static: %zu bytes of scratch needed, the static scratch holds %zu", need,
+                    GRAD_STATIC_BYTES);
+    // validate everything crbm_grad would before touching the device
+    st = check_lattice(params, L);
+    if (st != CRBM_OK) return st;
+    void* ptr = nullptr;
+    hipError_t e = grad_static_scratch(&ptr);
+    if (e != hipSuccess) return hip_fail(e, "crbm_grad_static: scratch address");
+    return crbm_grad(params, x, B, L, gF, dW, dhbias, dvbias, ptr, GRAD_STATIC_BYTES, stream);
+}
+
 crbm_status crbm_grad(const crbm_params* params, const int8_t* x, int32_t B, int32_t L, const float* gF, float* dW,
                       float* dhbias, float* dvbias, void* workspace, size_t workspace_bytes, void* stream)
 {

@@ -25,6 +25,10 @@ hipError_t launch_free_energy_dense(const float* W, const float* hb, const float
 size_t grad_dense_lds(int K, int nv);
 hipError_t launch_grad_dense(const float* W, const float* hb, int K, int nv, const int8_t* x, int B, const float* gF,
                              double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
+// crbm_grad_static: the device address of this GPU's static scratch of
+// GRAD_STATIC_BYTES (looked up once per device, with the device current)
+constexpr size_t GRAD_STATIC_BYTES = (size_t)8 << 20;
+hipError_t grad_static_scratch(void** ptr);
 hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, int open, int ne, const int8_t* x, int B,
                        int L, const float* gF, double* part, float* dW, float* dhb, float* dvb, hipStream_t s);
 

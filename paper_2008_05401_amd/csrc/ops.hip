@@ -4,6 +4,8 @@
 // ([banks][K][C][LW][LW], hidden biases [banks][K]), bank 0 for the bulk
 // columns, banks 1..ne for the hidden columns 0..ne-1 and ne+1..2ne for
 // L-ne..L-1; with `open` the windows stop at the column edge.
+#include <mutex>
+
 #include "device_common.h"
 #include "kitaev_eig.h"
 #include "ops.h"
@@ -362,6 +364,41 @@ hipError_t launch_grad(const float* W, const float* hb, int K, int C, int LW, in
     hipLaunchKernelGGL(grad_stage2, dim3((P + 255) / 256), dim3(256), 0, s, part, B, P, nb * K * C * LW * LW, nb * K,
                        dW, dhb, dvb);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of crbm_grad_static, the gradient entry point for callers that cannot
+// allocate: the per-sample partial gradients part[B][P] live in a file-scope
+// device array instead of a caller workspace.  Every GPU the library runs on
+// holds its own copy until the process ends; calls on one GPU share it.  In
+// host code the array's name is only a stand-in: its device address is looked
+// up once per device (with that device current) and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[GRAD_STATIC_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t grad_static_scratch(void** ptr)
+{
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace crbm

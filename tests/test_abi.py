@@ -150,3 +150,16 @@ def test_stats_record_layout(lib):
     assert _lib.STATS_DTYPE.itemsize == 160
     assert np.dtype(_lib.STATS_DTYPE).names[:4] == ("sweeps", "n_acc", "n_meas", "n_recheck")
     assert _lib.STATS_DTYPE.fields["F_bound"][1] == 136 and _lib.STATS_DTYPE.fields["n_swap"][1] == 144
+
+
+def test_grad_static_rejects_oversize_before_device_work(lib):
+    # 6000 samples x (8*25 + 8 + 1) parameters x 8 bytes exceed the 8 MiB static scratch:
+    # rejected on the host, no device call is made (this runs without a GPU)
+    _lib, _ = lib
+    with pytest.raises(_lib.CRBMError) as ei:
+        _lib.crbm_grad_static(_params(K=8, Lw=5), 0x1000, 6000, 16, 0x1000, 0x1000, 0x1000, 0x1000, None)
+    assert ei.value.status == _lib.CRBM_EBUDGET
+    assert "static scratch" in _lib.crbm_last_error()
+    with pytest.raises(_lib.CRBMError) as ei:
+        _lib.crbm_grad_static(_params(K=8, Lw=5), 0x1000, -1, 16, 0x1000, 0x1000, 0x1000, 0x1000, None)
+    assert ei.value.status == _lib.CRBM_EINVAL
