@@ -134,6 +134,14 @@ typedef struct {
     int8_t* rbm_state;     /* device [n_chains][C][L][L] or NULL; see below */
     void* workspace;       /* device, >= crbm_workspace_size() bytes */
     size_t workspace_bytes;
+    double mh_band_min;    /* >= 0: least half-width of the band of |log r - log u|
+                              inside which an MH decision is taken again on the
+                              exact route (Ising: FP64 free energies of both
+                              states; Kitaev: singular values of M by one-sided
+                              Jacobi for both states).  0 leaves the band to the
+                              rigorous error bounds of the fast route; a huge value
+                              sends every decision through the exact route (for
+                              tests).  The zero-initialised tail of a desc is 0. */
 } crbm_batch_desc;
 
 /* Per-chain record, kept in the workspace; read with crbm_read_stats.
@@ -154,7 +162,9 @@ typedef struct {
     double kE, kE2, kCf;  /* Kitaev sums of Ef, Ef^2, Cf */
     double F_bound;       /* bound on |F - F_exact| of the cached F (0: exact FP64) */
     int64_t n_swap;       /* accepted temperature swaps (crbm_tempering_swap) */
-    double reserved;
+    double S_bound;       /* Kitaev: bound on |S - S_exact| of the cached S from
+                             the error analysis of the eigen-step; 0 when S
+                             comes from the one-sided Jacobi re-check route */
 } crbm_chain_stats;
 
 typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
@@ -163,9 +173,10 @@ typedef struct crbm_ctx crbm_ctx; /* opaque host-side handle */
  * buffers: the bit-packed Ising kernel's filter tables, the Kitaev singular
  * values and eigen-step scratch).  Returns 0 for invalid arguments. Host
  * only, no device work.
- * Kitaev jobs run up to L = 24: up to L = 12 the eigen-step keeps M^T M in
- * LDS; beyond, the workspace also holds an N x N FP64 matrix per chain
- * (N = L^2; 2.7 MB per chain at L = 24). */
+ * Kitaev jobs run up to L = 24; the workspace holds an N x N FP64 matrix per
+ * chain (N = L^2; 2.7 MB per chain at L = 24, 166 KB at L = 12): M of the
+ * Jacobi re-check route, and beyond L = 12 also M^T M of the eigen-step
+ * (up to L = 12 that stays in LDS). */
 CRBM_API size_t crbm_workspace_size(const crbm_params* params, const crbm_batch_desc* desc);
 
 /* Create a job handle: copies `params`/`desc` (the pointed-to device buffers

@@ -32,7 +32,8 @@ class crbm_batch_desc(ct.Structure):
                 ("gibbs_k", ct.c_int32), ("burnin_sweeps", ct.c_int32), ("init_state", ct.c_int32),
                 ("chain_offset", ct.c_uint32), ("boundary", ct.c_int32), ("seed", ct.c_uint64),
                 ("J", ct.c_double * 3), ("T", ct.c_void_p), ("state", ct.c_void_p),
-                ("rbm_state", ct.c_void_p), ("workspace", ct.c_void_p), ("workspace_bytes", ct.c_size_t)]
+                ("rbm_state", ct.c_void_p), ("workspace", ct.c_void_p), ("workspace_bytes", ct.c_size_t),
+                ("mh_band_min", ct.c_double)]
 
 
 # crbm_chain_stats
@@ -40,7 +41,7 @@ STATS_DTYPE = np.dtype([
     ("sweeps", "<i8"), ("n_acc", "<i8"), ("n_meas", "<i8"), ("n_recheck", "<i8"),
     ("sumE", "<i8"), ("sumE2", "<i8"), ("sumM", "<i8"), ("sumAbsM", "<i8"), ("sumM2", "<i8"),
     ("E", "<i8"), ("F", "<f8"), ("S", "<f8"), ("Ef", "<f8"), ("Cf", "<f8"),
-    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"), ("F_bound", "<f8"), ("n_swap", "<i8"), ("reserved", "<f8"),
+    ("kE", "<f8"), ("kE2", "<f8"), ("kCf", "<f8"), ("F_bound", "<f8"), ("n_swap", "<i8"), ("S_bound", "<f8"),
 ])
 assert STATS_DTYPE.itemsize == 160
 

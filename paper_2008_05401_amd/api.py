@@ -84,11 +84,13 @@ class Job:
     replica exchanged with the physical state each sweep (App. B exchange
     correction); without it the replica is refreshed from the physical state.
     tempering_swap() performs one round of temperature swaps on the ladder grid
-    chain = rung * n_ladders + ladder."""
+    chain = rung * n_ladders + ladder.  mh_band_min widens the band of
+    |log r - log u| inside which an MH decision is taken again on the exact
+    route (a huge value sends every decision there)."""
 
     def __init__(self, params: CRBMParams, target: int, L: int, T, seed: int = 0, gibbs_k: int = 1,
                  burnin: int = 0, J=(1.0, 1.0, 1.0), state=None, chain_offset: int = 0, stream=None,
-                 replica: bool = False, rbm_state=None, boundary: int = 0):
+                 replica: bool = False, rbm_state=None, boundary: int = 0, mh_band_min: float = 0.0):
         dev = params.W.device
         self.params = params
         self.target = int(target)
@@ -121,7 +123,8 @@ class Job:
         self._desc = C.crbm_batch_desc(self.target, self.L, n, int(gibbs_k), int(burnin), init,
                                        int(chain_offset), int(boundary), int(seed), (C.ct.c_double * 3)(*J),
                                        self.T.data_ptr(), self.state.data_ptr(),
-                                       self.rbm_state.data_ptr() if self.rbm_state is not None else None, 0, 0)
+                                       self.rbm_state.data_ptr() if self.rbm_state is not None else None, 0, 0,
+                                       float(mh_band_min))
         ws = C.crbm_workspace_size(self._p, self._desc)
         if ws == 0:
             # let crbm_init produce the precise error message

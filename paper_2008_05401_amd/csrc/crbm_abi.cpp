@@ -111,6 +111,7 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     if (d->n_chains < 1) return fail(CRBM_EINVAL, "n_chains=%d must be >= 1", d->n_chains);
     if (d->gibbs_k < 1 || d->gibbs_k > 255) return fail(CRBM_EINVAL, "gibbs_k=%d outside [1,255]", d->gibbs_k);
     if (d->burnin_sweeps < 0) return fail(CRBM_EINVAL, "burnin_sweeps must be >= 0");
+    if (!(d->mh_band_min >= 0.0)) return fail(CRBM_EINVAL, "mh_band_min must be >= 0");
     if (d->target == CRBM_ISING && p->C != 1) return fail(CRBM_EINVAL, "Ising jobs need C=1 (got %d)", p->C);
     if (d->target == CRBM_KITAEV && d->L > kitaev_max_l())
         return fail(CRBM_EUNSUPPORTED, "Kitaev jobs support L <= %d (got %d)", kitaev_max_l(), d->L);
@@ -297,6 +298,7 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
     j.J0 = desc->J[0];
     j.J1 = desc->J[1];
     j.J2 = desc->J[2];
+    j.mh_band_min = desc->mh_band_min;
     j.seed = desc->seed;
     j.K = params->K;
     j.C = params->C;

@@ -192,7 +192,7 @@ struct ChainRec {
     double kE, kE2, kCf;
     double F_bound;     // bound on |F - F_exact| of the cached F
     long long n_swap;   // accepted temperature swaps
-    double reserved;
+    double S_bound;     // Kitaev: bound on |S - S_exact| of the cached S (0: Jacobi re-check route)
 };
 static_assert(sizeof(ChainRec) == 160, "record layout");
 

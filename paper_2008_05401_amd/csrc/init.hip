@@ -78,7 +78,7 @@ __global__ __launch_bounds__(BLOCK) void init_kernel(SweepLaunch P)
         ising_em_block(v, L, J.boundary, (long long*)red, E, M);
     } else {
         const int N = LL;
-        const KitaevBufs kb = kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_global_doubles(L) : nullptr, L);
+        const KitaevBufs kb = kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_chain_doubles(L) : nullptr, L);
         ko = kitaev_weight_block(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], kb, red);
         // singular values of the initial state, kept for temperature swaps
         if (J.eps)
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(BLOCK) void init_kernel(SweepLaunch P)
         R.S = ko.S;
         R.Ef = ko.Ef;
         R.Cf = ko.Cf;
+        R.S_bound = ko.B;
         J.rec[g] = R;
     }
 }

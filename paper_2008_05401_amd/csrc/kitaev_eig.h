@@ -2,7 +2,8 @@
 // honeycomb model (Sec. IV): S(u) = sum_lambda log 2cosh(beta eps_lambda / 2)
 // over the singular values eps of the Majorana hopping block M (N x N, N=L^2).
 //
-// GPU method (differs from a one-sided Jacobi SVD on purpose):
+// GPU method of the fast route (a one-sided Jacobi SVD of M, below, serves only
+// the rare re-checks of the MH test):
 //   1. A = M^T M is assembled directly from the bond variables (each white
 //      site has three black neighbours, so A has at most 7 non-zeros per row);
 //      up to L = 12 A is held in LDS as a packed lower triangle (N(N+1)/2
@@ -16,9 +17,27 @@
 //      per eigenvalue;
 //   4. eps_i = sqrt(max(lambda_i, 0)); S, the fermion energy and the
 //      fluctuation term are reduced over the workgroup.
-// Eigenvalues of A are accurate to ~N * 2^-52 * |A| in absolute terms; since
-// S depends on eps only through log 2cosh(beta eps / 2), whose derivative in
-// lambda is bounded by beta^2 / 8, the error of S stays far below 1e-6.
+//
+// Error bound carried with S (used by the MH test of the sweep).  Squaring M
+// costs accuracy: eigenvalues of A carry an absolute error dlam, and S depends
+// on lambda through f(lambda) = log 2cosh(beta sqrt(lambda) / 2), whose slope
+// f'(lambda) = (beta / 4) tanh(beta sqrt(lambda) / 2) / sqrt(lambda) is at most
+// (beta / 4) min(beta / 2, 1 / sqrt(lambda)) -- up to beta^2 / 8 for the small
+// singular values, 5000 at T = 0.005.  The bound is
+//   B_S = dlam sum_i (beta / 4) min(beta / 2, 1 / sqrt(max(lambda_i - dlam, 0)))
+//         + (N + 4) 2^-53 S,
+// the last term for the N log 2cosh evaluations and their sum.  dlam
+// (kitaev_dlam) takes the normwise backward error of Householder
+// tridiagonalisation in the textbook worst-case form, 4 N^2 2^-53 |A|_F (each
+// of the N - 2 similarity steps is exact for a matrix within ~4 n 2^-53 |A|_F,
+// n <= N the length of its dot products), with |A|_F <= |M|_F |M|_2 from the
+// couplings alone (so the bound needs no norm of the state), plus the Sturm
+// counts (exact for a tridiagonal matrix within a few ulp of T entrywise) and
+// the final bisection bracket.  By Weyl's theorem every eigenvalue then moves
+// by at most dlam.  The bound is a worst case: at L = 24, T = 0.005 it reaches
+// ~1e-3 while the observed errors against LAPACK are ~1e-9.  Where the MH test
+// falls inside the band, the decision is taken again from singular values of M
+// itself by one-sided Jacobi (kitaev_weight_jacobi), which never squares M.
 #pragma once
 #include "device_common.h"
 
@@ -29,18 +48,46 @@ __device__ __forceinline__ int tri_s(int i, int j) { return i >= j ? tri(i, j) :
 
 struct KitaevOut {
     double S, Ef, Cf;
+    double B;  // bound on |S - S_exact| (0 from the Jacobi route)
 };
+
+// |M|_2 <= 2 (|J_x| + |J_y| + |J_z|) (at most one bond of each kind per row and
+// column) and |M|_F <= 2 sqrt(N (J_x^2 + J_y^2 + J_z^2)); dlam bounds the
+// absolute error of every computed eigenvalue of A = M^T M (see above).
+__host__ __device__ inline double kitaev_dlam(int N, double Jx, double Jy, double Jz)
+{
+    const double u = 0x1p-53;
+    const double n2 = 2.0 * (fabs(Jx) + fabs(Jy) + fabs(Jz));
+    const double nf = 2.0 * sqrt((double)N * (Jx * Jx + Jy * Jy + Jz * Jz));
+    return 4.0 * (double)N * (double)N * u * nf * n2 + (16.0 * u + 1.2e-15) * n2 * n2;
+}
+
+// the share of one eigenvalue lambda (= eps^2) in B_S, without the factor dlam
+__device__ __forceinline__ double kitaev_bound_term(double lam, double beta, double dlam)
+{
+    const double lo = lam - dlam;
+    const double g = lo > 0.0 ? fmin(0.5 * beta, 1.0 / sqrt(lo)) : 0.5 * beta;
+    return 0.25 * beta * g;
+}
 
 constexpr int KITAEV_LDS_MAX_L = 12;  // A packed in LDS up to here
 constexpr int KITAEV_MAX_L = 24;      // A in a global scratch beyond
 
 __host__ __device__ inline bool kitaev_a_in_lds(int L) { return L <= KITAEV_LDS_MAX_L; }
 
-// doubles of the global scratch of one chain (0 when A lives in LDS)
+// doubles of the global scratch of A for one chain (0 when A lives in LDS)
 __host__ __device__ inline size_t kitaev_global_doubles(int L)
 {
     const size_t N = (size_t)L * L;
     return kitaev_a_in_lds(L) ? 0 : N * N;
+}
+
+// doubles of a chain's global scratch: N x N, for M of the Jacobi re-check and,
+// beyond L = 12, A of the eigen-step (used one after the other)
+__host__ __device__ inline size_t kitaev_chain_doubles(int L)
+{
+    const size_t N = (size_t)L * L;
+    return N * N;
 }
 
 // panel width of the blocked reduction used when A is global
@@ -409,7 +456,8 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     }
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double tol = 4e-16 * scale + 1e-300;
-    double S = 0.0, Ef = 0.0, Cf = 0.0;
+    const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
+    double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
     // four lanes per eigenvalue (a quad), each evaluating one of four interior
     // points: the bracket shrinks five-fold per step; the quad shares its four
     // counts through DPP quad permutations
@@ -487,12 +535,14 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
             Ef -= 0.5 * eps * tanh(xv);
             const double ch = cosh(xv);
             Cf += (xv * xv) / (ch * ch);
+            Bs += kitaev_bound_term(lam, beta, dlam);
         }
     }
     KitaevOut o;
     o.S = block_sum(S, red);
     o.Ef = block_sum(Ef, red);
     o.Cf = block_sum(Cf, red);
+    o.B = dlam * block_sum(Bs, red) + (double)(N + 4) * 0x1p-53 * o.S;
     return o;
 }
 
@@ -505,6 +555,123 @@ __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, 
                                             nullptr);
     return kitaev_weight_block_t<true>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps,
                                        b.vw);
+}
+
+// ---------------------------------------------------------------------------
+// The re-check route: S, E_f, C_f from the singular values of M itself by
+// one-sided (Hestenes) Jacobi, which never forms M^T M.  M is built column-major
+// in the chain's global scratch Mc (N x N doubles); column pairs are
+// orthogonalised in the round-robin order of a tournament (N' = N rounded up
+// to even players, player N' - 1 fixed, the others rotating), so the N'/2
+// pairs of a round are disjoint and run one per wave; a pair is rotated when
+// |x_p . x_q| > 1e-15 |x_p| |x_q|, and the sweeps stop once a whole sweep
+// rotates nothing (60 at most).  The singular values are then the column norms;
+// they go to eps_out (LDS or global).  Slow (O(N^3) per sweep) and only used for
+// the rare MH decisions inside the band of B_S.  nt a multiple of 64.
+// ---------------------------------------------------------------------------
+constexpr int KITAEV_JAC_MAXR = (KITAEV_MAX_L * KITAEV_MAX_L + 63) / 64;  // rows per lane
+
+__device__ __noinline__ KitaevOut kitaev_weight_jacobi(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
+                                          double Jz, double beta, double* __restrict__ Mc, double* eps_out,
+                                          double* red, int* flag)
+{
+    const int N = L * L;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+    // M[b][w] at Mc[w N + b]; thread b fills row b (its three bonds), so no two
+    // threads write one element
+    for (int q = tid; q < N * N; q += nt) Mc[q] = 0.0;
+    __syncthreads();
+    for (int b = tid; b < N; b += nt) {
+        const int i = b / L, j = b - (b / L) * L;
+        const double sz = (C == 3 ? v[2 * N + b] : v[b]) ? 1.0 : -1.0;
+        const double sx = C == 3 ? (v[b] ? 1.0 : -1.0) : 1.0;
+        const double sy = C == 3 ? (v[N + b] ? 1.0 : -1.0) : 1.0;
+        Mc[(size_t)b * N + b] += 2.0 * Jz * sz;
+        if (!(open_cols && j == L - 1)) Mc[(size_t)(i * L + (j + 1 == L ? 0 : j + 1)) * N + b] += 2.0 * Jx * sx;
+        Mc[(size_t)((i + 1 == L ? 0 : i + 1) * L + j) * N + b] += 2.0 * Jy * sy;
+    }
+    __syncthreads();
+    const int Np = N + (N & 1);
+    const int half = Np >> 1;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        int rotated = 0;
+        for (int r = 0; r + 1 < Np; ++r) {
+            for (int k = wid; k < half; k += nw) {
+                // players k and Np - 1 - k of round r
+                const int a = k, bq = Np - 1 - k;
+                int p = a == Np - 1 ? a : (a + r) % (Np - 1);
+                int q = bq == Np - 1 ? bq : (bq + r) % (Np - 1);
+                if (p >= N || q >= N) continue;  // the idle player of an odd N
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double* xp = Mc + (size_t)p * N;
+                double* xq = Mc + (size_t)q * N;
+                double cp[KITAEV_JAC_MAXR], cq[KITAEV_JAC_MAXR];
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int m = 0; m < KITAEV_JAC_MAXR; ++m) {
+                    const int row = lane + 64 * m;
+                    cp[m] = row < N ? xp[row] : 0.0;
+                    cq[m] = row < N ? xq[row] : 0.0;
+                    al += cp[m] * cp[m];
+                    be += cq[m] * cq[m];
+                    ga += cp[m] * cq[m];
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                rotated = 1;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+                for (int m = 0; m < KITAEV_JAC_MAXR; ++m) {
+                    const int row = lane + 64 * m;
+                    if (row < N) {
+                        xp[row] = cs * cp[m] - sn * cq[m];
+                        xq[row] = sn * cp[m] + cs * cq[m];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // stop after a sweep without rotations (every wave has seen the same rounds)
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        if (rotated && lane == 0) atomicOr(flag, 1);
+        __syncthreads();
+        const int any = *flag;
+        __syncthreads();
+        if (!any) break;
+    }
+    // column norms: one wave per column
+    double S = 0.0, Ef = 0.0, Cf = 0.0;
+    for (int c = wid; c < N; c += nw) {
+        const double* xc = Mc + (size_t)c * N;
+        double s2 = 0.0;
+        for (int row = lane; row < N; row += 64) s2 += xc[row] * xc[row];
+        s2 = wave_sum(s2);
+        if (lane == 0) {
+            const double eps = sqrt(s2);
+            eps_out[c] = eps;
+            const double xv = 0.5 * beta * eps;
+            S += log2cosh_d(xv);
+            Ef -= 0.5 * eps * tanh(xv);
+            const double ch = cosh(xv);
+            Cf += (xv * xv) / (ch * ch);
+        }
+    }
+    KitaevOut o;
+    o.S = block_sum(S, red);
+    o.Ef = block_sum(Ef, red);
+    o.Cf = block_sum(Cf, red);
+    o.B = 0.0;
+    return o;
 }
 
 }  // namespace crbm

@@ -19,9 +19,10 @@ struct JobDev {
     ChainRec* rec;
     double* eps;        // Kitaev: singular values of every chain's current state [n_chains][L*L]
     double* trace;      // per-sweep energy ring buffer [n_chains][trace_len] or nullptr
-    double* kitA;       // Kitaev beyond L = 12: per-chain global scratch of the eigen-step
+    double* kitA;       // Kitaev: per-chain N x N global scratch (Jacobi re-check; eigen-step beyond L = 12)
     unsigned char* tab; // bit-packed Ising kernel: the job's table block (built at crbm_init)
     double J0, J1, J2;
+    double mh_band_min; // least half-width of the MH re-check band
     uint64_t seed;
     int K, C, LW, target, L, n_chains, gibbs_k, burnin;
     uint32_t chain_offset;

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
 
     // ---------------------------------------------------------------- sweeps
     __shared__ long long sh_t0;
-    __shared__ int sh_acc;
+    __shared__ int sh_acc, sh_flag;
     __shared__ long long sh_M;
     __shared__ ChainRec R;  // touched by thread 0 only; in LDS so that no lane holds it in registers
     if (tid == 0) {
@@ -237,23 +237,59 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
         const double Fp = free_energy_block(Ws, hbs, vbs, vp, G, red);
         long long Ep = 0, Mp = 0;
         KitaevOut ko{0.0, 0.0, 0.0};
+        double* scratch = J.kitA ? J.kitA + (size_t)g * kitaev_chain_doubles(L) : nullptr;
         if (ising) ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
         else {
-            const KitaevBufs kb =
-                kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_global_doubles(L) : nullptr, L);
+            const KitaevBufs kb = kitaev_bufs(kit, scratch, L);
             ko = kitaev_weight_block(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
         }
+        double lu = 0.0;
         if (tid == 0) {
             const double logr = ising ? (-beta * J.J0 * (double)(Ep - R.E) + (Fp - R.F)) : ((ko.S - R.S) + (Fp - R.F));
-            const double lu = log(mh_uniform(J.seed, t, gid));
-            const int acc = gibbs_only ? 1 : (lu < logr);
+            lu = log(mh_uniform(J.seed, t, gid));
+            int acc = gibbs_only ? 1 : (lu < logr);
+            if (!ising) {
+                // Kitaev: the fast S of both states carries a rigorous bound (B_S); F is FP64
+                // with relative error far below 1e-12.  Inside the band both S come again
+                // from the Jacobi route.
+                double band = ko.B + R.S_bound + 1e-12 * (1.0 + fabs(ko.S) + fabs(R.S) + fabs(Fp) + fabs(R.F));
+                band = fmax(band, J.mh_band_min);
+                if (fabs(logr - lu) <= band) acc = 2;
+            }
             sh_acc = acc;
+        }
+        __syncthreads();
+        if (sh_acc == 2) {
+            // re-check: singular values of M by one-sided Jacobi for the proposal (into the
+            // LDS eps buffer, stored on acceptance) and, unless its cached S already came from
+            // this route, for the current state (its stored singular values are replaced)
+            ko = kitaev_weight_jacobi(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, scratch, kit, red, &sh_flag);
+            if (R.S_bound > 0.0) {
+                const KitaevOut kc = kitaev_weight_jacobi(vb3 + cur * C * LL, C, L, J.boundary, J.J0, J.J1, J.J2,
+                                                          beta, scratch, J.eps + (size_t)g * LL, red, &sh_flag);
+                if (tid == 0) {
+                    R.S = kc.S;
+                    R.Ef = kc.Ef;
+                    R.Cf = kc.Cf;
+                    R.S_bound = 0.0;
+                }
+            }
+            if (tid == 0) {
+                const double logr = (ko.S - R.S) + (Fp - R.F);
+                sh_acc = lu < logr;
+                R.n_recheck += 1;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int acc = sh_acc;
             if (acc) {
                 R.F = Fp;
                 R.E = Ep;
                 R.S = ko.S;
                 R.Ef = ko.Ef;
                 R.Cf = ko.Cf;
+                R.S_bound = ko.B;
                 R.n_acc += 1;
                 sh_M = Mp;
             } else {
@@ -311,7 +347,7 @@ template __global__ void sweep_generic_kernel<64>(SweepLaunch);
 
 int kitaev_max_l() { return KITAEV_MAX_L; }
 
-size_t kitaev_scratch_bytes(int L) { return kitaev_global_doubles(L) * sizeof(double); }
+size_t kitaev_scratch_bytes(int L) { return kitaev_chain_doubles(L) * sizeof(double); }
 
 size_t generic_lds_bytes(int K, int C, int LW, int L, int target, int banks, int dense)
 {

@@ -848,7 +848,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void sw
         if (tid == 0) {
             const double logr = -(1.0 / J.T[g]) * J.J0 * (double)(Ep - R.E) + (Fp - R.F);
             lu = sh_lu[it & (LU_CHUNK - 1)];
-            const double band = Bp + sh_Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F));
+            const double band =
+                fmax(Bp + sh_Bcur + 1e-12 * (1.0 + fabs(logr) + fabs(Fp) + fabs(R.F)), J.mh_band_min);
             sh_flag = J.target == 2 ? 1 : ((fabs(logr - lu) > band) ? (lu < logr ? 1 : 0) : 2);
         }
         __syncthreads();

@@ -5,6 +5,7 @@
 // which the pairs (rung q, rung q + 1), q = q0, q0 + 2, ..., of every ladder
 // are disjoint, so every pair is one independent wave.
 #include "device_common.h"
+#include "kitaev_eig.h"
 #include "sweep_common.h"
 
 namespace crbm {
@@ -27,7 +28,8 @@ __global__ __launch_bounds__(SWAP_NT) void tempering_swap_kernel(const JobDev* _
     const bool kitaev = J.target == 1;
 
     // log A = log P_a(x_b) + log P_b(x_a) - log P_a(x_a) - log P_b(x_b)
-    double logA, Sab = 0.0, Sba = 0.0, Efab = 0.0, Efba = 0.0, Cfab = 0.0, Cfba = 0.0;
+    double logA, Sab = 0.0, Sba = 0.0, Efab = 0.0, Efba = 0.0, Cfab = 0.0, Cfba = 0.0, Bab = 0.0, Bba = 0.0;
+    const double dlam = kitaev ? kitaev_dlam(LL, J.J0, J.J1, J.J2) : 0.0;
     if (!kitaev) {
         logA = J.J0 * (ba - bb) * (double)(Ra->E - Rb->E);
     } else {
@@ -42,6 +44,10 @@ __global__ __launch_bounds__(SWAP_NT) void tempering_swap_kernel(const JobDev* _
             const double ca = cosh(xa), cb = cosh(xb);
             Cfab += xa * xa / (ca * ca);
             Cfba += xb * xb / (cb * cb);
+            // error bounds of the new S (as in the eigen-step), for states whose singular
+            // values come from the fast route
+            Bab += kitaev_bound_term(eb[i] * eb[i], ba, dlam);
+            Bba += kitaev_bound_term(ea[i] * ea[i], bb, dlam);
         }
         Sab = wave_sum(Sab);
         Sba = wave_sum(Sba);
@@ -49,6 +55,8 @@ __global__ __launch_bounds__(SWAP_NT) void tempering_swap_kernel(const JobDev* _
         Efba = wave_sum(Efba);
         Cfab = wave_sum(Cfab);
         Cfba = wave_sum(Cfba);
+        Bab = wave_sum(Bab);
+        Bba = wave_sum(Bba);
         logA = Sab + Sba - Ra->S - Rb->S;
     }
     const double lu = log(uniform53(J.seed, round, J.chain_offset + (uint32_t)a, STREAM_PT));
@@ -92,12 +100,18 @@ __global__ __launch_bounds__(SWAP_NT) void tempering_swap_kernel(const JobDev* _
             Ra->E = Rb->E;
             Rb->E = E;
         } else {
+            // states whose S came from the Jacobi route keep S_bound = 0 (their singular
+            // values are the accurate ones)
+            const double Sbnd_a = Rb->S_bound > 0.0 ? dlam * Bab + (double)(LL + 4) * 0x1p-53 * Sab : 0.0;
+            const double Sbnd_b = Ra->S_bound > 0.0 ? dlam * Bba + (double)(LL + 4) * 0x1p-53 * Sba : 0.0;
             Ra->S = Sab;
             Ra->Ef = Efab;
             Ra->Cf = Cfab;
+            Ra->S_bound = Sbnd_a;
             Rb->S = Sba;
             Rb->Ef = Efba;
             Rb->Cf = Cfba;
+            Rb->S_bound = Sbnd_b;
         }
         Ra->n_swap += 1;
         Rb->n_swap += 1;
