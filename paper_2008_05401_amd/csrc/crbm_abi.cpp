@@ -128,9 +128,10 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
     } else {
         pl.kernel = K_GENERIC;
         pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
-        // the Kitaev eigen-step is latency-bound: one 16-wave workgroup per chain from N = 81 on,
-        // 8 waves below (at L = 6 5% faster than 4 waves, and 4 waves were 8% faster than 16)
-        if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = d->L <= 8 ? 512 : 1024;
+        // the Kitaev eigen-step is latency-bound: up to N = 64 four waves per chain (one
+        // wave tridiagonalises without workgroup barriers, all four bracket the
+        // eigenvalues), one 16-wave workgroup per chain beyond
+        if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = d->L <= 8 ? 256 : 1024;
         pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target, banks_of(p), p->dense);
     }
     if (pl.lds > kLdsLimit)

@@ -166,6 +166,34 @@ __device__ __forceinline__ Tv wave_sum(Tv v)
     return readlane_t(v, 0) + readlane_t(v, 32);
 }
 
+// The same sum for a double through DPP lane moves (VALU, no LDS round trips):
+// quad xor 1 and 2, the half-row and row mirrors give every lane its 16-lane
+// row sum, then the four row sums are read out.  Needs the whole wave active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// sum over the 16 lanes of a DPP row, in every lane of the row
+__device__ __forceinline__ double row16_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v = row16_sum(v);
+    return (readlane_t(v, 0) + readlane_t(v, 16)) + (readlane_t(v, 32) + readlane_t(v, 48));
+}
+
 // Workgroup sum; `red` is LDS scratch of >= nwaves entries.  Every thread
 // receives the total.  Contains two barriers.
 template <typename Tv>

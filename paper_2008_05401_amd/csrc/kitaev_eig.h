@@ -93,14 +93,32 @@ __host__ __device__ inline size_t kitaev_chain_doubles(int L)
 // panel width of the blocked reduction used when A is global
 constexpr int KITAEV_NB = 8;
 
+// One wave per configuration for N <= 64 (L <= 8) when the workgroup is a single
+// wave: A in LDS in full with an odd row stride (lane i owns row i), then d, e,
+// e^2 and the Householder vectors v and w.
+constexpr int KITAEV_WAVE_MAX_N = 64;
+// rows padded with zeros to a multiple of 8 columns (whole batches of eight
+// loads), plus one to make the row stride odd
+__host__ __device__ inline int kitaev_wave_cols(int N) { return (N + 7) & ~7; }
+__host__ __device__ inline int kitaev_wave_stride(int N) { return kitaev_wave_cols(N) + 1; }
+__host__ __device__ inline size_t kitaev_wave_lds_bytes(int L)
+{
+    const size_t N = (size_t)L * L, NC = (size_t)kitaev_wave_cols((int)N);
+    return sizeof(double) * (N * (size_t)kitaev_wave_stride((int)N) + 3 * N + 2 * NC);
+}
+
 // LDS region: [A packed, or the N eigenvalues when A is global | d | e | hv | p | (A global:)
 // the panel's reflectors V and their companions W, column-major, KITAEV_NB x N each, then
-// 16 waves x 2 KITAEV_NB partial sums and 2 KITAEV_NB reduced ones]
+// 16 waves x 2 KITAEV_NB partial sums and 2 KITAEV_NB reduced ones]; for N <= 64 large
+// enough for the one-wave layout as well
 __host__ __device__ inline size_t kitaev_lds_bytes(int L)
 {
     const size_t N = (size_t)L * L;
-    return sizeof(double) * (kitaev_a_in_lds(L) ? N * (N + 1) / 2 + 4 * N
-                                                : 5 * N + 2 * (size_t)KITAEV_NB * N + 34 * (size_t)KITAEV_NB);
+    const size_t blk = sizeof(double) * (kitaev_a_in_lds(L) ? N * (N + 1) / 2 + 4 * N
+                                                            : 5 * N + 2 * (size_t)KITAEV_NB * N + 34 * (size_t)KITAEV_NB);
+    if (N > (size_t)KITAEV_WAVE_MAX_N) return blk;
+    const size_t wv = kitaev_wave_lds_bytes(L);
+    return blk > wv ? blk : wv;
 }
 
 struct KitaevBufs {
@@ -125,6 +143,23 @@ __device__ inline KitaevBufs kitaev_bufs(double* lds, double* a_global, int L)
     return b;
 }
 
+// Address-space-qualified pointers for the out-of-line eigen-steps, so that they
+// address LDS with ds instructions and the global scratch with global ones
+// rather than with flat instructions
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) const uint8_t lds_u8c;
+typedef __attribute__((address_space(1))) double glb_f64;
+template <bool kFull>
+struct kit_a {
+    typedef lds_f64 type;
+};
+template <>
+struct kit_a<true> {
+    typedef glb_f64 type;
+};
+template <bool kFull>
+using kit_a_t = typename kit_a<kFull>::type;
+
 // Element (i, j) of A, i >= j for the packed form
 template <bool kFull>
 __device__ __forceinline__ int a_at(int i, int j, int N)
@@ -136,9 +171,10 @@ __device__ __forceinline__ int a_at(int i, int j, int N)
 // open_cols (Sec. IV.B): the x bonds from column L-1 to column 0 are absent.
 // kFull: A stored in full (N x N) rather than as a packed lower triangle.
 template <bool kFull>
-__device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
-                                           double Jz, double beta, double* A, double* d, double* e, double* hv,
-                                           double* p, double* red, double* eps_out, double* vw)
+__device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L, int open_cols, double Jx, double Jy,
+                                                        double Jz, double beta, kit_a_t<kFull>* A, lds_f64* d,
+                                                        lds_f64* e, lds_f64* hv, lds_f64* p, lds_f64* red,
+                                                        lds_f64* eps_out, lds_f64* vw)
 {
     const int N = L * L;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -213,8 +249,8 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
     const int grp = tid / G, gl = tid - (tid / G) * G, ngrp = nt / G;
     int slot = 0;
     auto reduce = [&](double x) -> double {
-        x = wave_sum(x);
-        double* r = red + 16 * slot;  // 16 waves at most
+        x = wave_sum_dpp(x);
+        lds_f64* r = red + 16 * slot;  // 16 waves at most
         slot ^= 1;
         if (lane == 0) r[wid] = x;
         __syncthreads();
@@ -234,10 +270,10 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
         // applies A22 -= V W^T + W V^T.  One read of the trailing matrix per column
         // plus one read-write per panel, instead of three passes per column.
         constexpr int NB = KITAEV_NB;
-        double* Vc = vw;           // V[l][i] = vw[l N + i]
-        double* Wc = vw + NB * N;  // W[l][i]
-        double* part = vw + 2 * NB * N;  // per-wave partial sums of t_W, t_V: [16 waves][2 NB]
-        double* tvw = part + 32 * NB;    // t_W[l], t_V[l] (2 NB doubles) after their reduction
+        lds_f64* Vc = vw;           // V[l][i] = vw[l N + i]
+        lds_f64* Wc = vw + NB * N;  // W[l][i]
+        lds_f64* part = vw + 2 * NB * N;  // per-wave partial sums of t_W, t_V: [16 waves][2 NB]
+        lds_f64* tvw = part + 32 * NB;    // t_W[l], t_V[l] (2 NB doubles) after their reduction
         for (int k0 = 0; k0 + 2 < N; k0 += NB) {
             const int nbk = min(NB, N - 2 - k0);
             for (int jj = 0; jj < nbk; ++jj) {
@@ -273,7 +309,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                 if (tid == 0) e[k] = alpha;
                 // v into column jj of V (hv stays as read: other waves may still be
                 // reading x0 from it); per-thread shares of t_W = W^T v and t_V = V^T v
-                double* vcol = Vc + jj * N;
+                lds_f64* vcol = Vc + jj * N;
                 double tw[NB], tv[NB];
 #pragma unroll
                 for (int l = 0; l < NB; ++l) tw[l] = tv[l] = 0.0;
@@ -309,7 +345,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                 // p = bet (A22 v - V t_W - W t_V), rows of A22 contiguous; G lanes per row
                 double pvl = 0.0;
                 for (int i = k + 1 + grp; i < N; i += ngrp) {
-                    const double* row = A + (size_t)i * N;
+                    const kit_a_t<kFull>* row = A + (size_t)i * N;
                     double a0 = 0.0, a1 = 0.0;
                     int j = k + 1 + gl;
                     for (; j + G < N; j += 2 * G) {
@@ -317,11 +353,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                         a1 += row[j + G] * vcol[j + G];
                     }
                     if (j < N) a0 += row[j] * vcol[j];
-                    double acc = a0 + a1;
-                    acc += swz_xor<8>(acc);
-                    acc += swz_xor<4>(acc);
-                    acc += swz_xor<2>(acc);
-                    acc += swz_xor<1>(acc);
+                    double acc = row16_sum(a0 + a1);
                     if (gl == 0) {
                         for (int l = 0; l < jj; ++l) acc -= Vc[l * N + i] * tvw[l] + Wc[l * N + i] * tvw[NB + l];
                         p[i] = bet * acc;
@@ -341,7 +373,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                     vi[l] = l < nbk ? Vc[l * N + i] : 0.0;
                     wi[l] = l < nbk ? Wc[l * N + i] : 0.0;
                 }
-                double* row = A + (size_t)i * N;
+                kit_a_t<kFull>* row = A + (size_t)i * N;
                 for (int j = kt + lane; j < N; j += 64) {
                     double a = row[j];
 #pragma unroll
@@ -388,11 +420,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
                 a1 += A[tri(j + G, i)] * hv[j + G];
             }
             if (j < N) a0 += A[tri(j, i)] * hv[j];
-            double acc = a0 + a1;
-            acc += swz_xor<8>(acc);
-            acc += swz_xor<4>(acc);
-            acc += swz_xor<2>(acc);
-            acc += swz_xor<1>(acc);
+            const double acc = row16_sum(a0 + a1);
             if (gl == 0) p[i] = bet * acc;
         }
         __syncthreads();
@@ -435,7 +463,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
         d[N - 1] = A[a_at<kFull>(N - 1, N - 1, N)];
     }
     __syncthreads();
-    double* ee = hv;  // e^2, hv is free now
+    lds_f64* ee = hv;  // e^2, hv is free now
     for (int i = tid; i + 1 < N; i += nt) ee[i] = e[i] * e[i];
     __syncthreads();
 
@@ -472,7 +500,7 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
             for (int q = 0; q < 4; ++q) xs[q] = lo + (double)(q + 1) * h;
             if (!(xs[0] > lo && xs[3] < hi && xs[0] < xs[1] && xs[1] < xs[2] && xs[2] < xs[3]))
                 break;  // no representable progress
-            const double x = xs[sub];
+            const double x = lo + (double)(sub + 1) * h;  // = xs[sub], without a dynamic index
             double p0 = 1.0, p1 = d[0] - x;
             if (p1 == 0.0) p1 = -0x1p-100;
             int cnt = p1 < 0.0;
@@ -539,6 +567,280 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
         }
     }
     KitaevOut o;
+    double* redg = (double*)red;
+    o.S = block_sum(S, redg);
+    o.Ef = block_sum(Ef, redg);
+    o.Cf = block_sum(Cf, redg);
+    o.B = dlam * block_sum(Bs, redg) + (double)(N + 4) * 0x1p-53 * o.S;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// The same eigen-step for N <= 64 (L <= 8) with a four-wave workgroup:
+//   - wave 0 alone assembles A = M^T M (LDS, full, odd row stride) and
+//     tridiagonalises it: lane i owns row i, so a Householder step is a wave
+//     reduction for the column norm, one row-times-vector product and one
+//     rank-2 update of the lane's own row, with the vectors v and w broadcast
+//     through LDS; the wave needs no workgroup barrier (wave_sync orders its
+//     LDS traffic), and the row loops run in batches of eight loads;
+//   - all four waves then bracket the eigenvalues: G lanes per eigenvalue
+//     (G <= 8, the largest with 4 floor(64 / G) >= N), each lane one interior
+//     point of the bracket, so it shrinks (G + 1)-fold per step; the group
+//     finds the first point whose Sturm count exceeds the eigenvalue's index
+//     from a ballot.
+// The bound on S is the one of kitaev_weight_block_t.  blockDim.x == 256; v, lds
+// and eps_out are LDS addresses.
+// ---------------------------------------------------------------------------
+constexpr int KITAEV_SMALL_NT = 256;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __host__ inline int kitaev_small_group(int N)
+{
+    int G = 8;
+    while (G > 1 && 4 * (64 / G) < N) --G;
+    return G;
+}
+
+__device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int open_cols, double Jx, double Jy,
+                                                 double Jz, lds_f64* A, lds_f64* d, lds_f64* e, lds_f64* vb,
+                                                 lds_f64* wb)
+{
+    const int N = L * L, NS = kitaev_wave_stride(N), NC = kitaev_wave_cols(N);
+    const int lane = threadIdx.x & 63;
+    // 1. A = M^T M; lane w fills A[w][w2] for w2 <= w and the mirror A[w2][w] (w2 < w),
+    //    which no other lane writes.  Rows are zero up to NC columns, and so are v and w
+    //    beyond N: the row loops then run whole batches of eight from an aligned start,
+    //    the entries j <= k of v and w being zero as well
+    if (lane < N)
+        for (int q = 0; q < NS; ++q) A[lane * NS + q] = 0.0;
+    if (lane >= N && lane < NC) {
+        vb[lane] = 0.0;
+        wb[lane] = 0.0;
+    }
+    wave_sync();
+    if (lane < N) {
+        const int w = lane;
+        const int i = w / L, j = w - (w / L) * L;
+        int bn[3];
+        bn[0] = w;
+        bn[1] = j == 0 ? (open_cols ? -1 : i * L + L - 1) : i * L + j - 1;
+        bn[2] = (i == 0 ? L - 1 : i - 1) * L + j;
+        for (int nb = 0; nb < 3; ++nb) {
+            const int b = bn[nb];
+            if (b < 0) continue;
+            bool dup = false;
+            for (int t = 0; t < nb; ++t) dup |= (bn[t] == b);
+            if (dup) continue;
+            const int bi = b / L, bj = b - (b / L) * L;
+            int wn[3];
+            double wv[3];
+            wn[0] = b;
+            wn[1] = bj + 1 == L ? (open_cols ? -1 : bi * L) : bi * L + bj + 1;
+            wn[2] = (bi + 1 == L ? 0 : bi + 1) * L + bj;
+            const double vz = C == 3 ? (v[2 * N + b] ? 1.0 : -1.0) : (v[b] ? 1.0 : -1.0);
+            const double vx = C == 3 ? (v[0 * N + b] ? 1.0 : -1.0) : 1.0;
+            const double vy = C == 3 ? (v[1 * N + b] ? 1.0 : -1.0) : 1.0;
+            wv[0] = 2.0 * Jz * vz;
+            wv[1] = 2.0 * Jx * vx;
+            wv[2] = 2.0 * Jy * vy;
+            double mbw = 0.0;
+            for (int t = 0; t < 3; ++t)
+                if (wn[t] == w) mbw += wv[t];
+            for (int t = 0; t < 3; ++t) {
+                const int w2 = wn[t];
+                if (w2 < 0) continue;
+                bool dupw = false;
+                for (int s2 = 0; s2 < t; ++s2) dupw |= (wn[s2] == w2);
+                if (dupw || w2 > w) continue;
+                double mbw2 = 0.0;
+                for (int s2 = 0; s2 < 3; ++s2)
+                    if (wn[s2] == w2) mbw2 += wv[s2];
+                A[w * NS + w2] += mbw * mbw2;
+                if (w2 != w) A[w2 * NS + w] += mbw * mbw2;
+            }
+        }
+    }
+    wave_sync();
+    // 2. Householder: step k annihilates column k below the subdiagonal
+    lds_f64* row = A + (lane < N ? lane : 0) * NS;
+    const bool own = lane < N;
+    for (int k = 0; k + 2 < N; ++k) {
+        const bool act = own && lane > k;
+        const double x = act ? row[k] : 0.0;
+        const double s2 = wave_sum_dpp(x * x);
+        const double x0 = readlane_t(x, k + 1);
+        const double rest = s2 - x0 * x0;
+        if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
+            if (lane == 0) {
+                d[k] = A[k * NS + k];
+                e[k] = x0;
+            }
+            continue;
+        }
+        const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
+        const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
+        const double vi = lane == k + 1 ? x0 - alpha : x;
+        if (own) vb[lane] = vi;
+        wave_sync();
+        // v_j = 0 for j <= k and j >= N, so the batches start at the aligned column below k + 1
+        const int j0 = (k + 1) & ~7;
+        double p = 0.0;
+        if (act) {
+            double a[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a[t] = 0.0;
+            for (int jj = j0; jj < NC; jj += 8) {
+                double r8[8], v8[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    r8[t] = row[jj + t];
+                    v8[t] = vb[jj + t];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) a[t] = fma(r8[t], v8[t], a[t]);
+            }
+            p = bet * (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+        }
+        const double kk2 = bet * wave_sum_dpp(p * vi);  // 2 kk
+        const double wi = p - 0.5 * kk2 * vi;
+        if (own) wb[lane] = wi;
+        wave_sync();
+        if (act) {
+            // the entries j <= k and j >= N get v_j = w_j = 0: written back unchanged
+            for (int jj = j0; jj < NC; jj += 8) {
+                double r8[8], v8[8], w8[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    r8[t] = row[jj + t];
+                    v8[t] = vb[jj + t];
+                    w8[t] = wb[jj + t];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) row[jj + t] = r8[t] - (vi * w8[t] + wi * v8[t]);
+            }
+        }
+        if (lane == 0) {
+            d[k] = A[k * NS + k];
+            e[k] = alpha;
+        }
+        wave_sync();
+    }
+    if (lane == 0) {
+        if (N >= 2) {
+            d[N - 2] = A[(N - 2) * NS + N - 2];
+            e[N - 2] = A[(N - 1) * NS + N - 2];
+        }
+        d[N - 1] = A[(N - 1) * NS + N - 1];
+    }
+    wave_sync();
+}
+
+__device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, int L, int open_cols, double Jx,
+                                                      double Jy, double Jz, double beta, double* lds, double* eps_out,
+                                                      double* red)
+{
+    const int N = L * L, NS = kitaev_wave_stride(N);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    lds_u8c* v = (lds_u8c*)v_;
+    const int NC = kitaev_wave_cols(N);
+    lds_f64* A = (lds_f64*)lds;
+    lds_f64* d = A + N * NS;
+    lds_f64* e = d + N;
+    lds_f64* ee = e + N;
+    lds_f64* vb = ee + N;
+    lds_f64* wb = vb + NC;
+    lds_f64* eps_l = (lds_f64*)eps_out;
+    if (wid == 0) kitaev_tridiag_wave(v, C, L, open_cols, Jx, Jy, Jz, A, d, e, vb, wb);
+    __syncthreads();
+    for (int i = tid; i + 1 < N; i += blockDim.x) ee[i] = e[i] * e[i];
+    __syncthreads();
+    // Gershgorin bracket of the whole spectrum
+    double glo = 0.0, ghi = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+        glo = fmin(glo, d[i] - r);
+        ghi = fmax(ghi, d[i] + r);
+    }
+    const double scale = fmax(fabs(glo), fabs(ghi));
+    const double tol = 4e-16 * scale + 1e-300;
+    const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
+    // eigenvalue idx: G lanes, lane `sub` evaluates the point lo + (sub + 1) h
+    const int G = kitaev_small_group(N), per_wave = 64 / G;
+    const int gi = lane / G, sub = lane - gi * G;
+    const int idx = wid * per_wave + gi;
+    const bool mine = gi < per_wave && idx < N;
+    double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
+    bool live = mine;
+    for (int it = 0; it < 128; ++it) {
+        const double h = (hi - lo) / (double)(G + 1);
+        const double x = lo + (double)(sub + 1) * h;
+        // done: bracket small enough, or no representable progress left
+        if (live && (!(hi - lo > tol) || !(lo + h > lo) || !(lo + (double)G * h < hi))) live = false;
+        if (!__any(live)) break;
+        int cnt = 0;
+        if (live) {
+            double p0 = 1.0, p1 = d[0] - x;
+            if (p1 == 0.0) p1 = -0x1p-100;
+            cnt = p1 < 0.0;
+            int i0 = 1;
+            for (; i0 + 7 < N; i0 += 8) {
+                double dv[8], ev[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    dv[u] = d[i0 + u];
+                    ev[u] = ee[i0 + u - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    double pn = fma(dv[u] - x, p1, -ev[u] * p0);
+                    if (pn == 0.0) pn = -0x1p-100 * p1;
+                    cnt += (pn < 0.0) != (p1 < 0.0);
+                    p0 = p1;
+                    p1 = pn;
+                }
+                const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                p0 *= f;
+                p1 *= f;
+            }
+            for (; i0 < N; ++i0) {
+                double pn = fma(d[i0] - x, p1, -ee[i0 - 1] * p0);
+                if (pn == 0.0) pn = -0x1p-100 * p1;
+                cnt += (pn < 0.0) != (p1 < 0.0);
+                p0 = p1;
+                p1 = pn;
+            }
+        }
+        // the group's first point with more than idx eigenvalues below it
+        const unsigned long long above = __ballot(live && cnt > idx);
+        const unsigned long long gmask = ((1ull << G) - 1ull) << (gi * G);
+        const unsigned long long mg = (above & gmask) >> (gi * G);
+        if (live) {
+            const int s0 = mg ? __builtin_ctzll(mg) : G;
+            const double nlo = lo + (double)s0 * h;
+            hi = s0 < G ? lo + (double)(s0 + 1) * h : hi;
+            lo = nlo;
+        }
+    }
+    double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
+    __syncthreads();  // every lane has read d and ee; eps may overwrite A
+    if (mine && sub == 0) {
+        const double lam = 0.5 * (lo + hi);
+        const double eps = sqrt(lam > 0.0 ? lam : 0.0);
+        eps_l[idx] = eps;
+        const double xv = 0.5 * beta * eps;
+        S = log2cosh_d(xv);
+        Ef = -0.5 * eps * tanh(xv);
+        const double ch = cosh(xv);
+        Cf = (xv * xv) / (ch * ch);
+        Bs = kitaev_bound_term(lam, beta, dlam);
+    }
+    KitaevOut o;
     o.S = block_sum(S, red);
     o.Ef = block_sum(Ef, red);
     o.Cf = block_sum(Cf, red);
@@ -550,11 +852,16 @@ __device__ KitaevOut kitaev_weight_block_t(const uint8_t* v, int C, int L, int o
 __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
                                                 double Jz, double beta, const KitaevBufs& b, double* red)
 {
+    if (blockDim.x == KITAEV_SMALL_NT && L * L <= KITAEV_WAVE_MAX_N)
+        return kitaev_weight_small(v, C, L, open_cols, Jx, Jy, Jz, beta, b.eps, b.eps, red);
+    lds_u8c* vl = (lds_u8c*)v;
     if (kitaev_a_in_lds(L))
-        return kitaev_weight_block_t<false>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps,
-                                            nullptr);
-    return kitaev_weight_block_t<true>(v, C, L, open_cols, Jx, Jy, Jz, beta, b.A, b.d, b.e, b.hv, b.p, red, b.eps,
-                                       b.vw);
+        return kitaev_weight_block_t<false>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (lds_f64*)b.A, (lds_f64*)b.d,
+                                            (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p, (lds_f64*)red,
+                                            (lds_f64*)b.eps, nullptr);
+    return kitaev_weight_block_t<true>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (glb_f64*)b.A, (lds_f64*)b.d,
+                                       (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p, (lds_f64*)red, (lds_f64*)b.eps,
+                                       (lds_f64*)b.vw);
 }
 
 // ---------------------------------------------------------------------------

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __res
     const int N = L * L;
     double* red = (double*)smem;
     double* A = red + 64;
-    uint8_t* v = (uint8_t*)(A + N * (N + 1) / 2 + 4 * N);
+    uint8_t* v = (uint8_t*)A + kitaev_lds_bytes(L);  // past every layout of the eigen-step
     const int8_t* xs = x + (size_t)blockIdx.x * C * N;
     for (int q = threadIdx.x; q < C * N; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();

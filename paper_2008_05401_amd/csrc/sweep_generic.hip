@@ -173,61 +173,79 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             uint8_t* vd = vb3 + dst * C * LL;
             // hidden pass
             const int nh = G.dense ? K : K * LL, ngh = (nh + 3) >> 2;
-            for (int gi = tid; gi < ngh; gi += NT) {
-                const u32x4 r = philox10((uint32_t)gi, t, gid, STREAM_HID | ((uint32_t)sub << 8), k0, k1);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const int q = 4 * gi + w;
-                    if (q < nh && G.dense) {
-                        const float a = dense_hidden_f(Ws, hbs, vs, nvis, q);
-                        bool near;
-                        bool on = bernoulli_fast(a, word_of(r, w), dAh[q], near);
-                        if (near) {
-                            on = bernoulli_exact(dense_hidden_d(Ws, hbs, vs, nvis, q), word_of(r, w));
-                            ++nre;
-                        }
-                        h[q] = on;
-                    } else if (q < nh) {
-                        const int k = q / LL, rr = q - k * LL, i = rr / L, j = rr - i * L;
-                        const float a = preact_hidden_f(Ws, hbs, vs, G, k, i, j);
-                        bool near;
-                        bool on = bernoulli_fast(a, word_of(r, w), dAh[G.bank(j) * K + k], near);
-                        if (near) {
-                            on = bernoulli_exact(preact_hidden_d(Ws, hbs, vs, G, k, i, j), word_of(r, w));
-                            ++nre;
-                        }
-                        h[q] = on;
+            const uint32_t tagh = STREAM_HID | ((uint32_t)sub << 8), tagv = STREAM_VIS | ((uint32_t)sub << 8);
+            auto hid_unit = [&](int q, uint32_t word) {
+                if (G.dense) {
+                    const float a = dense_hidden_f(Ws, hbs, vs, nvis, q);
+                    bool near;
+                    bool on = bernoulli_fast(a, word, dAh[q], near);
+                    if (near) {
+                        on = bernoulli_exact(dense_hidden_d(Ws, hbs, vs, nvis, q), word);
+                        ++nre;
                     }
+                    h[q] = on;
+                } else {
+                    const int k = q / LL, rr = q - k * LL, i = rr / L, j = rr - i * L;
+                    const float a = preact_hidden_f(Ws, hbs, vs, G, k, i, j);
+                    bool near;
+                    bool on = bernoulli_fast(a, word, dAh[G.bank(j) * K + k], near);
+                    if (near) {
+                        on = bernoulli_exact(preact_hidden_d(Ws, hbs, vs, G, k, i, j), word);
+                        ++nre;
+                    }
+                    h[q] = on;
+                }
+            };
+            if (ngh < NT) {
+                // fewer Philox blocks than lanes: a lane per unit (each lane draws its unit's block)
+                for (int q = tid; q < nh; q += NT) {
+                    const u32x4 r = philox10((uint32_t)q >> 2, t, gid, tagh, k0, k1);
+                    hid_unit(q, word_of(r, q & 3));
+                }
+            } else {
+                for (int gi = tid; gi < ngh; gi += NT) {
+                    const u32x4 r = philox10((uint32_t)gi, t, gid, tagh, k0, k1);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        if (4 * gi + w < nh) hid_unit(4 * gi + w, word_of(r, w));
                 }
             }
             __syncthreads();
             // visible pass
             const int nv = C * LL, ngv = (nv + 3) >> 2;
-            for (int gi = tid; gi < ngv; gi += NT) {
-                const u32x4 r = philox10((uint32_t)gi, t, gid, STREAM_VIS | ((uint32_t)sub << 8), k0, k1);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const int q = 4 * gi + w;
-                    if (q < nv && G.dense) {
-                        const float b = dense_visible_f(Ws, vbs, h, K, nvis, q);
-                        bool near;
-                        bool on = bernoulli_fast(b, word_of(r, w), dAv[q], near);
-                        if (near) {
-                            on = bernoulli_exact(dense_visible_d(Ws, vbs, h, K, nvis, q), word_of(r, w));
-                            ++nre;
-                        }
-                        vd[q] = on;
-                    } else if (q < nv) {
-                        const int c = q / LL, rr = q - c * LL, x = rr / L, y = rr - x * L;
-                        const float b = preact_visible_f(Ws, vbs, h, G, c, x, y);
-                        bool near;
-                        bool on = bernoulli_fast(b, word_of(r, w), dAv[c], near);
-                        if (near) {
-                            on = bernoulli_exact(preact_visible_d(Ws, vbs, h, G, c, x, y), word_of(r, w));
-                            ++nre;
-                        }
-                        vd[q] = on;
+            auto vis_unit = [&](int q, uint32_t word) {
+                if (G.dense) {
+                    const float b = dense_visible_f(Ws, vbs, h, K, nvis, q);
+                    bool near;
+                    bool on = bernoulli_fast(b, word, dAv[q], near);
+                    if (near) {
+                        on = bernoulli_exact(dense_visible_d(Ws, vbs, h, K, nvis, q), word);
+                        ++nre;
                     }
+                    vd[q] = on;
+                } else {
+                    const int c = q / LL, rr = q - c * LL, x = rr / L, y = rr - x * L;
+                    const float b = preact_visible_f(Ws, vbs, h, G, c, x, y);
+                    bool near;
+                    bool on = bernoulli_fast(b, word, dAv[c], near);
+                    if (near) {
+                        on = bernoulli_exact(preact_visible_d(Ws, vbs, h, G, c, x, y), word);
+                        ++nre;
+                    }
+                    vd[q] = on;
+                }
+            };
+            if (ngv < NT) {
+                for (int q = tid; q < nv; q += NT) {
+                    const u32x4 r = philox10((uint32_t)q >> 2, t, gid, tagv, k0, k1);
+                    vis_unit(q, word_of(r, q & 3));
+                }
+            } else {
+                for (int gi = tid; gi < ngv; gi += NT) {
+                    const u32x4 r = philox10((uint32_t)gi, t, gid, tagv, k0, k1);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        if (4 * gi + w < nv) vis_unit(4 * gi + w, word_of(r, w));
                 }
             }
             __syncthreads();
