@@ -12,9 +12,9 @@
 //      every access of the reduction below is then a contiguous row;
 //   2. Householder reduction of A to a symmetric tridiagonal matrix (d, e),
 //      column by column in LDS, in panels of 8 columns when A is global;
-//   3. every eigenvalue lambda_i of the tridiagonal matrix by five-fold
-//      multisection on the Sturm count (division-free recurrence), four lanes
-//      per eigenvalue;
+//   3. every eigenvalue lambda_i of the tridiagonal matrix by multisection on
+//      the Sturm count (division-free recurrence), a group of up to eight lanes
+//      per eigenvalue (kitaev_eigs_groups);
 //   4. eps_i = sqrt(max(lambda_i, 0)); S, the fermion energy and the
 //      fluctuation term are reduced over the workgroup.
 //
@@ -165,6 +165,110 @@ template <bool kFull>
 __device__ __forceinline__ int a_at(int i, int j, int N)
 {
     return kFull ? i * N + j : tri(i, j);
+}
+
+// ---------------------------------------------------------------------------
+// Every eigenvalue of the symmetric tridiagonal matrix (d, e), e2 = e^2, by
+// multisection on the Sturm count, over the whole workgroup: a group of G
+// adjacent lanes per eigenvalue (G <= 8, the largest with
+// nwaves floor(64 / G) >= N, further rounds when even G = 1 leaves eigenvalues
+// over), lane `sub` of the group evaluating the point lo + (sub + 1) h,
+// h = (hi - lo) / (G + 1), so the bracket shrinks (G + 1)-fold per step; the
+// group finds its first point whose count exceeds the eigenvalue's index from
+// a ballot.  The count comes from the division-free three-term recurrence
+// p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, p_i = det(T_i - x), one
+// eigenvalue below x per sign change of p_i / p_{i-1}; an exact zero is
+// replaced by -2^-100 p_{i-1} (the sign convention of the ratio form), and the
+// pair is rescaled by 2^-+100 every eight steps to stay in range; the operands
+// of eight steps are read from LDS before the eight dependent steps.  The
+// first lane of each group adds log 2cosh(beta eps / 2), the fermion energy,
+// the fluctuation term and the share of eps in the bound B_S (without the factor
+// dlam) to S, Ef, Cf, Bs, and stores eps = sqrt(max(lambda, 0)) to eps_out
+// after a workgroup barrier (eps_out may alias the dead matrix, never d or e2).
+// ---------------------------------------------------------------------------
+__device__ __host__ inline int kitaev_group_size(int N, int nwaves)
+{
+    int G = 8;
+    while (G > 1 && nwaves * (64 / G) < N) --G;
+    return G;
+}
+
+__device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, int N, double glo, double ghi,
+                                          double tol, double beta, double dlam, lds_f64* eps_out, double& S,
+                                          double& Ef, double& Cf, double& Bs)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    const double scale = fmax(fabs(glo), fabs(ghi));
+    const int G = kitaev_group_size(N, nw), per_wave = 64 / G, cap = nw * per_wave;
+    const int gi = lane / G, sub = lane - gi * G;
+    const unsigned long long gmask = ((1ull << G) - 1ull) << (gi * G);
+    const int rounds = (N + cap - 1) / cap;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int idx = rd * cap + wid * per_wave + gi;
+        const bool mine = gi < per_wave && idx < N;
+        double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
+        bool live = mine;
+        for (int it = 0; it < 256; ++it) {
+            const double h = (hi - lo) / (double)(G + 1);
+            const double x = lo + (double)(sub + 1) * h;
+            // done: bracket small enough, or no representable progress left
+            if (live && (!(hi - lo > tol) || !(lo + h > lo) || !(lo + (double)G * h < hi))) live = false;
+            if (!__any(live)) break;
+            int cnt = 0;
+            if (live) {
+                double p0 = 1.0, p1 = d[0] - x;
+                if (p1 == 0.0) p1 = -0x1p-100;
+                cnt = p1 < 0.0;
+                int i0 = 1;
+                for (; i0 + 7 < N; i0 += 8) {
+                    double dv[8], ev[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        dv[u] = d[i0 + u];
+                        ev[u] = e2[i0 + u - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        double pn = fma(dv[u] - x, p1, -ev[u] * p0);
+                        if (pn == 0.0) pn = -0x1p-100 * p1;
+                        cnt += (pn < 0.0) != (p1 < 0.0);
+                        p0 = p1;
+                        p1 = pn;
+                    }
+                    const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                    p0 *= f;
+                    p1 *= f;
+                }
+                for (; i0 < N; ++i0) {
+                    double pn = fma(d[i0] - x, p1, -e2[i0 - 1] * p0);
+                    if (pn == 0.0) pn = -0x1p-100 * p1;
+                    cnt += (pn < 0.0) != (p1 < 0.0);
+                    p0 = p1;
+                    p1 = pn;
+                }
+            }
+            // the group's first point with more than idx eigenvalues below it
+            const unsigned long long mg = (__ballot(live && cnt > idx) & gmask) >> (gi * G);
+            if (live) {
+                const int s0 = mg ? __builtin_ctzll(mg) : G;
+                const double nlo = lo + (double)s0 * h;
+                hi = s0 < G ? lo + (double)(s0 + 1) * h : hi;
+                lo = nlo;
+            }
+        }
+        __syncthreads();  // every lane has read d and e2 of this round; eps may overwrite the matrix
+        if (mine && sub == 0) {
+            const double lam = 0.5 * (lo + hi);
+            const double eps = sqrt(lam > 0.0 ? lam : 0.0);
+            eps_out[idx] = eps;
+            const double xv = 0.5 * beta * eps;
+            S += log2cosh_d(xv);
+            Ef -= 0.5 * eps * tanh(xv);
+            const double ch = cosh(xv);
+            Cf += (xv * xv) / (ch * ch);
+            Bs += kitaev_bound_term(lam, beta, dlam);
+        }
+    }
 }
 
 // v: 0/1 bytes of the proposal, C channels ([3][L][L] = x,y,z bonds, or [1][L][L] = z bonds).
@@ -467,105 +571,17 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
     for (int i = tid; i + 1 < N; i += nt) ee[i] = e[i] * e[i];
     __syncthreads();
 
-    // 3. eigenvalue idx of the tridiagonal matrix by multisection on the Sturm
-    //    count: a quad of lanes per eigenvalue, one interior point per lane,
-    //    the bracket cut five-fold per step.  The count comes from the division-free
-    //    three-term recurrence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2},
-    //    p_i = det(T_i - x), one eigenvalue below x per sign change of
-    //    p_i / p_{i-1}; an exact zero is replaced by -2^-100 p_{i-1} (the sign
-    //    convention of the ratio form), and the pair is rescaled by 2^-+100
-    //    every eight steps to stay in range.  Within a lane the operands of
-    //    eight steps are read from LDS before the eight dependent steps.
-    double glo = 0.0, ghi = 0.0;  // Gershgorin bracket of the whole spectrum
+    // 3. the eigenvalues (kitaev_eigs_groups), within the Gershgorin bracket of the whole spectrum
+    double glo = 0.0, ghi = 0.0;
     for (int i = 0; i < N; ++i) {
         const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
         glo = fmin(glo, d[i] - r);
         ghi = fmax(ghi, d[i] + r);
     }
-    const double scale = fmax(fabs(glo), fabs(ghi));
-    const double tol = 4e-16 * scale + 1e-300;
+    const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
-    // four lanes per eigenvalue (a quad), each evaluating one of four interior
-    // points: the bracket shrinks five-fold per step; the quad shares its four
-    // counts through DPP quad permutations
-    const int sub = tid & 3;
-    for (int idx = tid >> 2; idx < N; idx += nt >> 2) {
-        double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
-        for (int it = 0; it < 96; ++it) {
-            if (!(hi - lo > tol)) break;
-            const double h = (hi - lo) * 0.2;
-            double xs[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) xs[q] = lo + (double)(q + 1) * h;
-            if (!(xs[0] > lo && xs[3] < hi && xs[0] < xs[1] && xs[1] < xs[2] && xs[2] < xs[3]))
-                break;  // no representable progress
-            const double x = lo + (double)(sub + 1) * h;  // = xs[sub], without a dynamic index
-            double p0 = 1.0, p1 = d[0] - x;
-            if (p1 == 0.0) p1 = -0x1p-100;
-            int cnt = p1 < 0.0;
-            auto step = [&](double di, double e2) {
-                double pn = fma(di - x, p1, -e2 * p0);
-                if (pn == 0.0) pn = -0x1p-100 * p1;
-                cnt += (pn < 0.0) != (p1 < 0.0);
-                p0 = p1;
-                p1 = pn;
-            };
-            auto rescale = [&]() {
-                const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
-                p0 *= f;
-                p1 *= f;
-            };
-            // the first (N - 1) % 8 steps one by one, then blocks of eight whose
-            // operands are loaded together ahead of the recurrence
-            const int r0 = (N - 1) & 7;
-            for (int i = 1; i <= r0; ++i) step(d[i], ee[i - 1]);
-            rescale();
-            for (int i0 = r0 + 1; i0 < N; i0 += 8) {
-                double dv[8], ev[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    dv[u] = d[i0 + u];
-                    ev[u] = ee[i0 + u - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) step(dv[u], ev[u]);
-                rescale();
-            }
-            // counts of the quad's four points (quad_perm broadcasts of lanes 0..3)
-            int c[4];
-            c[0] = __builtin_amdgcn_update_dpp(0, cnt, 0x00, 0xF, 0xF, false);
-            c[1] = __builtin_amdgcn_update_dpp(0, cnt, 0x55, 0xF, 0xF, false);
-            c[2] = __builtin_amdgcn_update_dpp(0, cnt, 0xAA, 0xF, 0xF, false);
-            c[3] = __builtin_amdgcn_update_dpp(0, cnt, 0xFF, 0xF, 0xF, false);
-            // eigenvalue idx lies below x iff more than idx eigenvalues do
-            if (c[0] > idx) {
-                hi = xs[0];
-            } else if (c[1] > idx) {
-                lo = xs[0];
-                hi = xs[1];
-            } else if (c[2] > idx) {
-                lo = xs[1];
-                hi = xs[2];
-            } else if (c[3] > idx) {
-                lo = xs[2];
-                hi = xs[3];
-            } else {
-                lo = xs[3];
-            }
-        }
-        if (sub == 0) {
-            const double lam = 0.5 * (lo + hi);
-            const double eps = sqrt(lam > 0.0 ? lam : 0.0);
-            if (eps_out) eps_out[idx] = eps;  // may alias a packed A: it is dead after the tridiagonalisation
-            const double xv = 0.5 * beta * eps;
-            S += log2cosh_d(xv);
-            Ef -= 0.5 * eps * tanh(xv);
-            const double ch = cosh(xv);
-            Cf += (xv * xv) / (ch * ch);
-            Bs += kitaev_bound_term(lam, beta, dlam);
-        }
-    }
+    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_out, S, Ef, Cf, Bs);
     KitaevOut o;
     double* redg = (double*)red;
     o.S = block_sum(S, redg);
@@ -583,11 +599,7 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
 //     rank-2 update of the lane's own row, with the vectors v and w broadcast
 //     through LDS; the wave needs no workgroup barrier (wave_sync orders its
 //     LDS traffic), and the row loops run in batches of eight loads;
-//   - all four waves then bracket the eigenvalues: G lanes per eigenvalue
-//     (G <= 8, the largest with 4 floor(64 / G) >= N), each lane one interior
-//     point of the bracket, so it shrinks (G + 1)-fold per step; the group
-//     finds the first point whose Sturm count exceeds the eigenvalue's index
-//     from a ballot.
+//   - all four waves then bracket the eigenvalues (kitaev_eigs_groups).
 // The bound on S is the one of kitaev_weight_block_t.  blockDim.x == 256; v, lds
 // and eps_out are LDS addresses.
 // ---------------------------------------------------------------------------
@@ -598,13 +610,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __host__ inline int kitaev_small_group(int N)
-{
-    int G = 8;
-    while (G > 1 && 4 * (64 / G) < N) --G;
-    return G;
 }
 
 __device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int open_cols, double Jx, double Jy,
@@ -767,79 +772,10 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
         glo = fmin(glo, d[i] - r);
         ghi = fmax(ghi, d[i] + r);
     }
-    const double scale = fmax(fabs(glo), fabs(ghi));
-    const double tol = 4e-16 * scale + 1e-300;
+    const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
-    // eigenvalue idx: G lanes, lane `sub` evaluates the point lo + (sub + 1) h
-    const int G = kitaev_small_group(N), per_wave = 64 / G;
-    const int gi = lane / G, sub = lane - gi * G;
-    const int idx = wid * per_wave + gi;
-    const bool mine = gi < per_wave && idx < N;
-    double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
-    bool live = mine;
-    for (int it = 0; it < 128; ++it) {
-        const double h = (hi - lo) / (double)(G + 1);
-        const double x = lo + (double)(sub + 1) * h;
-        // done: bracket small enough, or no representable progress left
-        if (live && (!(hi - lo > tol) || !(lo + h > lo) || !(lo + (double)G * h < hi))) live = false;
-        if (!__any(live)) break;
-        int cnt = 0;
-        if (live) {
-            double p0 = 1.0, p1 = d[0] - x;
-            if (p1 == 0.0) p1 = -0x1p-100;
-            cnt = p1 < 0.0;
-            int i0 = 1;
-            for (; i0 + 7 < N; i0 += 8) {
-                double dv[8], ev[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    dv[u] = d[i0 + u];
-                    ev[u] = ee[i0 + u - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    double pn = fma(dv[u] - x, p1, -ev[u] * p0);
-                    if (pn == 0.0) pn = -0x1p-100 * p1;
-                    cnt += (pn < 0.0) != (p1 < 0.0);
-                    p0 = p1;
-                    p1 = pn;
-                }
-                const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
-                p0 *= f;
-                p1 *= f;
-            }
-            for (; i0 < N; ++i0) {
-                double pn = fma(d[i0] - x, p1, -ee[i0 - 1] * p0);
-                if (pn == 0.0) pn = -0x1p-100 * p1;
-                cnt += (pn < 0.0) != (p1 < 0.0);
-                p0 = p1;
-                p1 = pn;
-            }
-        }
-        // the group's first point with more than idx eigenvalues below it
-        const unsigned long long above = __ballot(live && cnt > idx);
-        const unsigned long long gmask = ((1ull << G) - 1ull) << (gi * G);
-        const unsigned long long mg = (above & gmask) >> (gi * G);
-        if (live) {
-            const int s0 = mg ? __builtin_ctzll(mg) : G;
-            const double nlo = lo + (double)s0 * h;
-            hi = s0 < G ? lo + (double)(s0 + 1) * h : hi;
-            lo = nlo;
-        }
-    }
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
-    __syncthreads();  // every lane has read d and ee; eps may overwrite A
-    if (mine && sub == 0) {
-        const double lam = 0.5 * (lo + hi);
-        const double eps = sqrt(lam > 0.0 ? lam : 0.0);
-        eps_l[idx] = eps;
-        const double xv = 0.5 * beta * eps;
-        S = log2cosh_d(xv);
-        Ef = -0.5 * eps * tanh(xv);
-        const double ch = cosh(xv);
-        Cf = (xv * xv) / (ch * ch);
-        Bs = kitaev_bound_term(lam, beta, dlam);
-    }
+    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_l, S, Ef, Cf, Bs);
     KitaevOut o;
     o.S = block_sum(S, red);
     o.Ef = block_sum(Ef, red);
