@@ -95,7 +95,11 @@ class Job:
         self.params = params
         self.target = int(target)
         self.L = int(L)
-        self.T = torch.as_tensor(np.asarray(T, np.float64).reshape(-1), device=dev).contiguous()
+        if torch.is_tensor(T) and T.device == dev:
+            # a device tensor is used as it is (no host round trip)
+            self.T = T.to(torch.float64).reshape(-1).contiguous()
+        else:
+            self.T = torch.as_tensor(np.asarray(T, np.float64).reshape(-1), device=dev).contiguous()
         n = int(self.T.numel())
         self.n_chains = n
         shape = (n, params.C, self.L, self.L)

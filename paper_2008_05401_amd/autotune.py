@@ -41,7 +41,7 @@ def candidates(L: int):
     return out
 
 
-def time_candidate(L, K, Lw, rows, nt, n_chains, sweeps, reps=3, seed=0):
+def time_candidate(L, K, Lw, rows, nt, n_chains, sweeps, reps=3, seed=0, warm_s=0.2):
     import torch
 
     from . import api, workloads
@@ -49,8 +49,12 @@ def time_candidate(L, K, Lw, rows, nt, n_chains, sweeps, reps=3, seed=0):
     f = workloads.random_filters(K, 1, Lw, 0.05, seed=seed)
     T = np.linspace(1.5, 3.5, n_chains)
     job = api.Job(api.CRBMParams.from_filters(f), api.ISING, L, T, seed=seed)
-    job.run(10)
-    torch.cuda.synchronize()
+    # run the candidate until the GPU holds its clocks under it (a cold start or a
+    # few milliseconds of idle cost 10-20% on the first launches), then time it
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        job.run(sweeps)
+        torch.cuda.synchronize()
     times = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)

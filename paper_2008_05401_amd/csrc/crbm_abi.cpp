@@ -203,7 +203,8 @@ crbm_status check_job_list(crbm_ctx* const* ctxs, int n_ctx)
 
 crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode, hipStream_t s)
 {
-    // group by kernel variant (and thread count / LDS) and chunk by MAX_JOBS_PER_LAUNCH
+    // group by kernel variant (and thread count / LDS), larger lattices first, and chunk by
+    // MAX_JOBS_PER_LAUNCH
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -215,7 +216,9 @@ crbm_status launch_jobs(crbm_ctx* const* ctxs, int n, int n_sweeps, int mode, hi
         if (pa.kernel == K_ISING_FAST && ctxs[a]->params.K != ctxs[b]->params.K) return ctxs[a]->params.K < ctxs[b]->params.K;
         if (pa.kernel == K_ISING_FAST && ctxs[a]->params.Lw != ctxs[b]->params.Lw)
             return ctxs[a]->params.Lw < ctxs[b]->params.Lw;
-        return false;
+        // within a launch the larger lattices first: workgroups are dispatched in
+        // index order, so the longest ones start earliest (longest-processing-time order)
+        return ctxs[a]->desc.L > ctxs[b]->desc.L;
     });
     size_t i = 0;
     while (i < order.size()) {

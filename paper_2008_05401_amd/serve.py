@@ -6,20 +6,30 @@ include/crbm.h).  The server
 
 * admits arriving jobs in FIFO order as soon as their HBM footprint (state,
   workspace, temperatures, filters) fits the budget next to the jobs already
-  resident;
-* keeps every admitted job's chains resident on the GPU and advances all of
-  them together: each scheduling step issues one `crbm_propose_accept_many`
-  call (a handful of kernel launches shared by all jobs) for a block of
-  sweeps no larger than any active job's remaining work, so jobs that arrive
-  while others run join the next step;
-* detects completion without blocking the GPU: after a job's last block its
+  resident, and keeps every admitted job's chains resident on the GPU;
+* splits jobs by cost.  A small job (L^2 below `large_sites`) runs all its
+  sweeps in one launch, shared with the other small jobs admitted in the same
+  step, on the small-job stream.  Large jobs advance together in blocks of
+  `large_block` sweeps on their own stream, a new block being issued when the
+  previous one is done (at most `max_inflight` ahead), so a large job that
+  arrives joins at the next block and the workgroups of large jobs free their
+  compute units every few milliseconds.  The two streams (default priority)
+  overlap on the device: small jobs do not wait behind the block length of an
+  L = 256 job, which is what set the tail when every job advanced in lock step;
+* within a launch the library orders the chains by descending lattice size,
+  so the longest workgroups are dispatched first;
+* puts a new job's filters and temperatures on the device through an idle
+  admission stream, so that admitting a job never waits for launches already
+  queued on the job streams;
+* detects completion without blocking the GPU: after a job's last sweeps its
   per-chain records are copied on the device and an event is recorded; the
   host polls the event, then copies the small record buffer out and frees the
   job's memory.
 
 Latency of a job = completion time - arrival time (queueing included).
-Results do not depend on the mix: random numbers are indexed by (seed, chain,
-sweep), so a job gives the same chains alone and in any batch.
+Results do not depend on the mix, the stream or the block lengths: random
+numbers are indexed by (seed, chain, sweep), so a job gives the same chains
+alone and in any batch.
 """
 from __future__ import annotations
 
@@ -71,62 +81,106 @@ def footprint_bytes(spec: workloads.Job, K: int = 8, Lw: int = 5) -> int:
 @dataclass
 class Server:
     budget_bytes: int = 16 << 30
-    max_block: int = 10
-    max_inflight: int = 2
+    large_block: int = 4          # sweeps per launch of the large jobs
+    large_sites: int = 128 * 128  # a job with L^2 >= large_sites is large
+    max_inflight: int = 2         # large-job blocks issued ahead of the GPU
     K: int = 8
     Lw: int = 5
     keep_state: bool = False
     results: list = field(default_factory=list)
 
+    def _admit(self, sp, stream, now):
+        # The filters and temperatures go to the device on an idle admission stream:
+        # a host-to-device copy from pageable memory waits for its stream, and the
+        # job streams hold the running launches.  The job's stream then waits for
+        # that stream before crbm_init.
+        f = job_filters(sp, self.K, self.Lw)
+        with torch.cuda.stream(self._s_admit):
+            p = api.CRBMParams.from_filters(f)
+            T = torch.full((sp.n_chains,), sp.T, dtype=torch.float64, device="cuda")
+            ev = torch.cuda.Event()
+            ev.record(self._s_admit)
+        stream.wait_event(ev)
+        with torch.cuda.stream(stream):
+            job = api.Job(p, api.ISING, sp.L, T, seed=sp.seed, burnin=sp.n_sweeps // 10)
+        res = JobResult(sp.job_id, sp.arrival_s, admit_s=now())
+        return _Active(sp, job, res, footprint_bytes(sp, self.K, self.Lw), sp.n_sweeps)
+
+    @staticmethod
+    def _finish(jobs, stream, finishing):
+        """Device-side copies of the records of jobs whose last sweeps are issued, and an event."""
+        with torch.cuda.stream(stream):
+            for a in jobs:
+                a.rec_dev = a.job.stats_device()
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        for a in jobs:
+            a.event = ev
+            finishing.append(a)
+        return ev
+
     def run(self, specs, time_scale: float = 1.0):
-        """Serve `specs` (sorted by arrival); arrival times are seconds from the start."""
+        """Serve `specs` (sorted by arrival); arrival times are seconds from the start,
+        multiplied by time_scale."""
         specs = sorted(specs, key=lambda s: s.arrival_s)
         pending = list(specs)
         waiting = []            # arrived, not admitted
-        active = []             # resident
-        finishing = []          # last block issued, waiting for its event
+        large = []              # resident large jobs with sweeps left
+        finishing = []          # last sweeps issued, waiting for their event
+        inflight = []           # events of the large-job blocks issued
         used = 0
-        inflight = []
+        s_small = torch.cuda.Stream()
+        s_large = torch.cuda.Stream()
+        self._s_admit = torch.cuda.Stream()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
-        while pending or waiting or active or finishing:
+        while pending or waiting or large or finishing:
             t = now()
             while pending and pending[0].arrival_s * time_scale <= t:
-                waiting.append(pending.pop(0))
+                sp = pending.pop(0)
+                sp = workloads.Job(sp.job_id, sp.arrival_s * time_scale, sp.L, sp.T, sp.n_chains, sp.n_sweeps,
+                                   sp.seed)
+                waiting.append(sp)
             # FIFO admission under the HBM budget
+            new_small = []
             while waiting:
                 sp = waiting[0]
                 fp = footprint_bytes(sp, self.K, self.Lw)
-                if used + fp > self.budget_bytes and (active or finishing):
+                if used + fp > self.budget_bytes and (large or finishing or new_small):
                     break
                 waiting.pop(0)
-                f = job_filters(sp, self.K, self.Lw)
-                job = api.Job(api.CRBMParams.from_filters(f), api.ISING, sp.L, np.full(sp.n_chains, sp.T),
-                              seed=sp.seed, burnin=sp.n_sweeps // 10)
-                res = JobResult(sp.job_id, sp.arrival_s * time_scale, admit_s=now())
-                active.append(_Active(sp, job, res, fp, sp.n_sweeps))
+                is_large = sp.L * sp.L >= self.large_sites
+                a = self._admit(sp, s_large if is_large else s_small, now)
                 used += fp
-            if active:
-                block = min(self.max_block, min(a.remaining for a in active))
-                api.run_many([a.job for a in active], block)
-                still, ended = [], []
-                for a in active:
+                (large if is_large else new_small).append(a)
+            # small jobs: all their sweeps in one shared launch per sweep count
+            if new_small:
+                by_len = {}
+                for a in new_small:
+                    by_len.setdefault(a.remaining, []).append(a)
+                for n_sw, group in by_len.items():
+                    if n_sw > 0:
+                        api.run_many([a.job for a in group], n_sw)
+                    for a in group:
+                        a.remaining = 0
+                    self._finish(group, s_small, finishing)
+            # large jobs: the next block when fewer than max_inflight are outstanding
+            inflight = [ev for ev in inflight if not ev.query()]
+            if large and len(inflight) < self.max_inflight:
+                block = min(self.large_block, min(a.remaining for a in large))
+                if block > 0:
+                    api.run_many([a.job for a in large], block)
+                for a in large:
                     a.remaining -= block
-                    if a.remaining == 0:
-                        a.rec_dev = a.job.stats_device()  # device-side copy of the records
-                        ended.append(a)
-                    else:
-                        still.append(a)
-                ev = torch.cuda.Event()
-                ev.record()  # after the sweeps and the record copies
-                inflight.append(ev)
-                for a in ended:
-                    a.event = ev
-                    finishing.append(a)
-                active = still
-                # bound the queue of work issued ahead of the GPU
-                while len(inflight) > self.max_inflight:
-                    inflight.pop(0).synchronize()
+                ended = [a for a in large if a.remaining == 0]
+                large = [a for a in large if a.remaining > 0]
+                if ended:
+                    inflight.append(self._finish(ended, s_large, finishing))
+                else:
+                    with torch.cuda.stream(s_large):
+                        ev = torch.cuda.Event()
+                        ev.record(s_large)
+                    inflight.append(ev)
             # completions
             done = []
             for a in finishing:
@@ -142,13 +196,14 @@ class Server:
                     done.append(a)
             if done:
                 finishing = [a for a in finishing if a not in done]
-            if not active and not done:
-                if finishing:
-                    time.sleep(0.0002)
+            if not done and not new_small:
+                if finishing or inflight:
+                    time.sleep(0.0001)
                 elif pending and not waiting:
                     dt = pending[0].arrival_s * time_scale - now()
                     if dt > 0:
                         time.sleep(min(dt, 0.01))
+        torch.cuda.synchronize()
         return self.results
 
 
@@ -157,6 +212,7 @@ def latency_summary(results, warmup_s: float = 0.0):
     if lat.size == 0:
         return {"jobs": 0}
     return {"jobs": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p90_ms": float(np.percentile(lat, 90) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
 
 

@@ -1,6 +1,7 @@
 """Serving: every job's chains are identical whether it runs alone, in the
-continuous-batching server next to other jobs, or in the plain
-one-chain-per-launch form; admission respects the HBM budget."""
+continuous-batching server next to other jobs (small jobs in one launch on one
+stream, large jobs in blocks on another), or in the plain one-chain-per-launch
+form; admission respects the HBM budget."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,9 @@ def _alone(api, serve, sp):
 def test_served_results_equal_alone(mods, budget):
     api, serve = mods
     specs = _specs()
-    srv = serve.Server(budget_bytes=budget, max_block=4, keep_state=True)
+    # L >= 32 counts as large here, so both the one-launch small path and the
+    # blocked large path (two streams) serve part of the stream
+    srv = serve.Server(budget_bytes=budget, large_block=4, large_sites=32 * 32, keep_state=True)
     res = {r.job_id: r for r in srv.run(specs)}
     assert sorted(res) == [s.job_id for s in specs]
     for sp in specs:
@@ -73,7 +76,7 @@ def test_plain_form_equals_batched(mods):
 def test_served_matches_oracle(mods, orc):
     api, serve = mods
     sp = WL.Job(job_id=3, arrival_s=0.0, L=8, T=2.0, n_chains=6, n_sweeps=15, seed=33)
-    srv = serve.Server(max_block=4, keep_state=True)
+    srv = serve.Server(large_block=4, large_sites=8 * 8, keep_state=True)
     r = srv.run([sp])[0]
     f = serve.job_filters(sp)
     ch = orc.Chains(orc.CRBM(f.W, f.hbias, f.vbias), orc.ISING, sp.L, np.full(sp.n_chains, sp.T), seed=sp.seed,
