@@ -233,7 +233,10 @@ def served(n_jobs, rate, warmup_s, capacity, loads=(0.3, 0.6, 0.9), plain_jobs=3
     for each fraction of `capacity` (the batched throughput measured above),
     n_sweeps = load * capacity / (rate * mean(n_chains L^2)); p50/p90/p99 of
     completion - arrival over the jobs arriving after `warmup_s`, the jobs/s
-    and site-sweeps/s achieved.  Beside it, the plain form (each chain alone, one
+    and site-sweeps/s achieved; each measured job is then run alone on the idle
+    GPU, and the slowdown latency / alone time is summarised as well (job sizes
+    n_chains L^2 span three decades, so raw p99/p50 is at least the spread of
+    the alone times).  Beside it, the plain form (each chain alone, one
     launch per chain, jobs one after another) on a few jobs at the middle load."""
     import torch
 
@@ -255,8 +258,19 @@ def served(n_jobs, rate, warmup_s, capacity, loads=(0.3, 0.6, 0.9), plain_jobs=3
         span = max(r.done_s for r in measured) - min(r.arrival_s for r in measured)
         by_id = {sp.job_id: sp for sp in specs}
         site_sweeps = sum(by_id[r.job_id].n_chains * by_id[r.job_id].L ** 2 * n_sweeps for r in measured)
-        small = [r.latency_s for r in measured if by_id[r.job_id].L ** 2 < srv.large_sites]
-        large = [r.latency_s for r in measured if by_id[r.job_id].L ** 2 >= srv.large_sites]
+        small = [r.latency_s for r in measured if srv.lane_of(by_id[r.job_id].L) == 0]
+        medium = [r.latency_s for r in measured if srv.lane_of(by_id[r.job_id].L) == 1]
+        large = [r.latency_s for r in measured if srv.lane_of(by_id[r.job_id].L) == 2]
+        # each measured job alone on the idle GPU (admission, set-up, sweeps, read-back):
+        # its service floor; slowdown = latency / floor
+        alone = {}
+        for r in measured:
+            sp = by_id[r.job_id]
+            one = serve.Server(budget_bytes=16 << 30).run(
+                [WL.Job(sp.job_id, 0.0, sp.L, sp.T, sp.n_chains, sp.n_sweeps, sp.seed)])
+            alone[r.job_id] = one[0].latency_s
+        floor = np.array([alone[r.job_id] for r in measured])
+        slow = np.array([r.latency_s / alone[r.job_id] for r in measured])
         points.append({
             "offered_load": load, "sweeps_per_job": n_sweeps,
             "offered_site_sweeps_per_s": rate * mean_nl2 * n_sweeps,
@@ -266,8 +280,14 @@ def served(n_jobs, rate, warmup_s, capacity, loads=(0.3, 0.6, 0.9), plain_jobs=3
             "achieved_load": site_sweeps / span / capacity, "wall_s": wall,
             "small_jobs_p50_ms": float(np.percentile(small, 50) * 1e3) if small else None,
             "small_jobs_p99_ms": float(np.percentile(small, 99) * 1e3) if small else None,
+            "medium_jobs_p50_ms": float(np.percentile(medium, 50) * 1e3) if medium else None,
+            "medium_jobs_p99_ms": float(np.percentile(medium, 99) * 1e3) if medium else None,
             "large_jobs_p50_ms": float(np.percentile(large, 50) * 1e3) if large else None,
-            "large_jobs_p99_ms": float(np.percentile(large, 99) * 1e3) if large else None})
+            "large_jobs_p99_ms": float(np.percentile(large, 99) * 1e3) if large else None,
+            "alone_p50_ms": float(np.percentile(floor, 50) * 1e3), "alone_p99_ms": float(np.percentile(floor, 99) * 1e3),
+            "alone_p99_over_p50": float(np.percentile(floor, 99) / np.percentile(floor, 50)),
+            "slowdown_p50": float(np.percentile(slow, 50)), "slowdown_p90": float(np.percentile(slow, 90)),
+            "slowdown_p99": float(np.percentile(slow, 99)), "slowdown_mean": float(slow.mean())})
     mid = points[len(points) // 2]["sweeps_per_job"]
     sample = WL.served_job_stream(total, rate_per_s=rate, n_sweeps=mid, seed=0)[-plain_jobs:]
     t1 = time.perf_counter()

@@ -349,6 +349,17 @@ crbm_status crbm_init(crbm_ctx** out, const crbm_params* params, const crbm_batc
         delete c;
         return hip_fail(e, "init launch");
     }
+    if (pl.kernel == K_ISING_FAST) {
+        if (ising_init_fe_lds_bytes(params->K, params->Lw, desc->L) > kLdsLimit) {
+            delete c;
+            return fail(CRBM_EUNSUPPORTED, "initial free energy needs too much LDS");
+        }
+        e = launch_ising_init_fe(c->job_dev, desc->n_chains, params->K, params->Lw, desc->L, c->stream);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "free-energy launch");
+        }
+    }
     *out = c;
     return CRBM_OK;
 }

@@ -1,7 +1,7 @@
 // init.hip -- per-chain set-up of a job: optional initial state from the INIT
 // Philox stream (i.i.d. +-1, as the Binomial(p=0.5) start of Alg. 1), the FP64
-// CRBM free energy of the state and its target (Ising E, M or Kitaev S, E_f,
-// C_f); sums zeroed.  One workgroup per chain, byte-per-unit lattice in LDS.
+// CRBM free energy of the state (left to a kernel of the bit-packed sweep for
+// its jobs) and its target (Ising E, M or Kitaev S, E_f, C_f); sums zeroed.  One workgroup per chain, byte-per-unit lattice in LDS.
 #include "device_common.h"
 #include "generic_blocks.h"
 #include "kitaev_eig.h"
@@ -71,7 +71,9 @@ __global__ __launch_bounds__(BLOCK) void init_kernel(SweepLaunch P)
         for (int q = tid; q < C * LL; q += NT) v[q] = state[q] > 0;
     }
     __syncthreads();
-    const double F = free_energy_block(Ws, hbs, vbs, v, G, red);
+    // jobs of the bit-packed Ising kernel get F from its table-driven FP64 routine,
+    // launched right after this kernel
+    const double F = J.tab ? 0.0 : free_energy_block(Ws, hbs, vbs, v, G, red);
     long long E = 0, M = 0;
     KitaevOut ko{0.0, 0.0, 0.0};
     if (J.target != 1) {

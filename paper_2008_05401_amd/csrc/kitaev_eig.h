@@ -751,7 +751,7 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
                                                       double* red)
 {
     const int N = L * L, NS = kitaev_wave_stride(N);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, wid = tid >> 6;
     lds_u8c* v = (lds_u8c*)v_;
     const int NC = kitaev_wave_cols(N);
     lds_f64* A = (lds_f64*)lds;

@@ -57,6 +57,10 @@ size_t ising_fast_lds_bytes(int K, int LW, int L);
 size_t ising_tab_bytes(int K, int LW);
 // build the table block of a job (job descriptor already on the device)
 hipError_t launch_ising_tables(const JobDev* job_dev, hipStream_t s);
+// FP64 free energy of every chain's initial state into its record (after the
+// generic initialisation, on the same stream); the LDS it needs
+size_t ising_init_fe_lds_bytes(int K, int LW, int L);
+hipError_t launch_ising_init_fe(const JobDev* job_dev, int n_chains, int K, int LW, int L, hipStream_t s);
 hipError_t launch_ising_fast(const SweepLaunch& P, int K, int LW, int BH, int n_blocks, size_t lds, int nt,
                              hipStream_t s);
 

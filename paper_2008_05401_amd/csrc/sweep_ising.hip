@@ -141,6 +141,55 @@ __global__ __launch_bounds__(256) void ising_tables_kernel(const JobDev* __restr
 }
 
 // ---------------------------------------------------------------------------
+// FP64 free energy (Eq. free-energy_CRBM) of each chain's initial state for the
+// jobs of the bit-packed kernel, one workgroup per chain, run by crbm_init after
+// the generic initialisation (which leaves F to this kernel).  The state goes
+// into a bit plane as in the sweep, and F comes from the same exact routine as
+// the sweep's MH re-check: per site and channel the FP64 subset sums of the
+// filter rows, the softplus terms in product form.
+// ---------------------------------------------------------------------------
+template <int LW>
+__global__ __launch_bounds__(256) void ising_init_fe_kernel(const JobDev* __restrict__ jd)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const JobDev& J = *jd;
+    const int g = blockIdx.x;
+    const int K = J.K, L = J.L, lgL = 31 - __builtin_clz(L), tsz = K * LW * (1 << LW);
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int RS = (L >= 32 ? (L >> 5) : 1) + 1;
+    const IsingTabLayout tl = ising_tab_layout(K, LW);
+    {
+        const uint4* __restrict__ src = (const uint4*)J.tab;
+        uint4* dst = (uint4*)smem;
+        for (int q = tid; q < tl.bytes / 16; q += NT) dst[q] = src[q];
+    }
+    const float* hbl = (const float*)smem + 3 * tsz + 6 * K;
+    const float* Wl = hbl + K;
+    const IsingTabConst& TC = *(const IsingTabConst*)(smem + tl.off_const);
+    const double* T64 = ising_fast_t64(K, LW) ? (const double*)(smem + tl.off_t64) : nullptr;
+    double* red = (double*)(smem + tl.bytes);
+    uint32_t* pl = (uint32_t*)(red + 64);
+    const int8_t* state = J.state + (size_t)g * L * L;
+    // +-1 int8 lattice -> bit plane, four sites per lane (every lane of a wave
+    // takes part in store_nibble)
+    const int lgq = lgL - 2, nq = (L * L) >> 2, nrounds = (nq + NT - 1) / NT;
+    for (int r = 0; r < nrounds; ++r) {
+        const int Q = r * NT + tid;
+        const bool active = Q < nq;
+        const int i = active ? (Q >> lgq) : 0, m = active ? (Q & ((L >> 2) - 1)) : 0;
+        uint32_t nib = 0;
+        if (active) {
+            const uint32_t w4 = ~*(const uint32_t*)(state + (i << lgL) + 4 * m);
+            nib = ((w4 >> 7) & 1u) | ((w4 >> 14) & 2u) | ((w4 >> 21) & 4u) | ((w4 >> 28) & 8u);
+        }
+        store_nibble(pl, RS, L, i, m, nib, active);
+    }
+    __syncthreads();
+    const double F = free_energy_exact<LW>(Wl, hbl, TC.vb_raw, pl, RS, L, K, red, TC.dc, T64);
+    if (tid == 0) J.rec[g].F = F;
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 bool ising_fast_supported(int K, int LW, int L)
@@ -176,6 +225,28 @@ size_t ising_fast_lds_bytes(int K, int LW, int L)
 hipError_t launch_ising_tables(const JobDev* job_dev, hipStream_t s)
 {
     hipLaunchKernelGGL(ising_tables_kernel, dim3(1), dim3(256), 0, s, job_dev);
+    return hipGetLastError();
+}
+
+size_t ising_init_fe_lds_bytes(int K, int LW, int L)
+{
+    const size_t RS = (L >= 32 ? (size_t)(L >> 5) : 1) + 1;
+    return ising_tab_bytes(K, LW) + 64 * 8 + (size_t)L * RS * 4;
+}
+
+hipError_t launch_ising_init_fe(const JobDev* job_dev, int n_chains, int K, int LW, int L, hipStream_t s)
+{
+    const size_t lds = ising_init_fe_lds_bytes(K, LW, L);
+    const dim3 grid(n_chains), block(256);
+    switch (LW) {
+    case 1: hipLaunchKernelGGL(ising_init_fe_kernel<1>, grid, block, lds, s, job_dev); break;
+    case 2: hipLaunchKernelGGL(ising_init_fe_kernel<2>, grid, block, lds, s, job_dev); break;
+    case 3: hipLaunchKernelGGL(ising_init_fe_kernel<3>, grid, block, lds, s, job_dev); break;
+    case 4: hipLaunchKernelGGL(ising_init_fe_kernel<4>, grid, block, lds, s, job_dev); break;
+    case 5: hipLaunchKernelGGL(ising_init_fe_kernel<5>, grid, block, lds, s, job_dev); break;
+    case 6: hipLaunchKernelGGL(ising_init_fe_kernel<6>, grid, block, lds, s, job_dev); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -7,15 +7,16 @@ include/crbm.h).  The server
 * admits arriving jobs in FIFO order as soon as their HBM footprint (state,
   workspace, temperatures, filters) fits the budget next to the jobs already
   resident, and keeps every admitted job's chains resident on the GPU;
-* splits jobs by cost.  A small job (L^2 below `large_sites`) runs all its
-  sweeps in one launch, shared with the other small jobs admitted in the same
-  step, on the small-job stream.  Large jobs advance together in blocks of
-  `large_block` sweeps on their own stream, a new block being issued when the
-  previous one is done (at most `max_inflight` ahead), so a large job that
-  arrives joins at the next block and the workgroups of large jobs free their
-  compute units every few milliseconds.  The two streams (default priority)
-  overlap on the device: small jobs do not wait behind the block length of an
-  L = 256 job, which is what set the tail when every job advanced in lock step;
+* splits jobs by lattice size into three lanes, each on its own stream
+  (default priority), which overlap on the device.  A small job (L^2 below
+  `medium_sites`) or a medium one (below `large_sites`) runs all its sweeps in
+  one launch, shared with the jobs of its lane admitted in the same step.
+  Large jobs advance together in blocks of `large_block` sweeps, a new block
+  being issued when the previous one is done (at most `max_inflight` ahead), so
+  a large job that arrives joins at the next block and the workgroups of large
+  jobs free their compute units every few milliseconds.  A job thus waits
+  behind launches of its own size class only: neither behind the block length
+  of the largest lattices nor, for the smallest, behind a medium launch;
 * within a launch the library orders the chains by descending lattice size,
   so the longest workgroups are dispatched first;
 * puts a new job's filters and temperatures on the device through an idle
@@ -81,18 +82,25 @@ def footprint_bytes(spec: workloads.Job, K: int = 8, Lw: int = 5) -> int:
 @dataclass
 class Server:
     budget_bytes: int = 16 << 30
-    large_block: int = 4          # sweeps per launch of the large jobs
-    large_sites: int = 128 * 128  # a job with L^2 >= large_sites is large
-    max_inflight: int = 2         # large-job blocks issued ahead of the GPU
+    large_block: int = 4            # sweeps per launch of the large jobs
+    medium_sites: int = 128 * 128   # L^2 >= medium_sites: medium lane
+    large_sites: int = 256 * 256    # L^2 >= large_sites: large lane (blocks)
+    max_inflight: int = 2           # large-job blocks issued ahead of the GPU
     K: int = 8
     Lw: int = 5
     keep_state: bool = False
     results: list = field(default_factory=list)
 
+    def lane_of(self, L: int) -> int:
+        """0: small, 1: medium (each a job's sweeps in one launch), 2: large (blocks)."""
+        if L * L >= self.large_sites:
+            return 2
+        return 1 if L * L >= min(self.medium_sites, self.large_sites) else 0
+
     def _admit(self, sp, stream, now):
         # The filters and temperatures go to the device on an idle admission stream:
         # a host-to-device copy from pageable memory waits for its stream, and the
-        # job streams hold the running launches.  The job's stream then waits for
+        # lane streams hold the running launches.  The job's stream then waits for
         # that stream before crbm_init.
         f = job_filters(sp, self.K, self.Lw)
         with torch.cuda.stream(self._s_admit):
@@ -129,8 +137,7 @@ class Server:
         finishing = []          # last sweeps issued, waiting for their event
         inflight = []           # events of the large-job blocks issued
         used = 0
-        s_small = torch.cuda.Stream()
-        s_large = torch.cuda.Stream()
+        streams = [torch.cuda.Stream() for _ in range(3)]
         self._s_admit = torch.cuda.Stream()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
@@ -142,28 +149,28 @@ class Server:
                                    sp.seed)
                 waiting.append(sp)
             # FIFO admission under the HBM budget
-            new_small = []
+            new = ([], [])
             while waiting:
                 sp = waiting[0]
                 fp = footprint_bytes(sp, self.K, self.Lw)
-                if used + fp > self.budget_bytes and (large or finishing or new_small):
+                if used + fp > self.budget_bytes and (large or finishing or new[0] or new[1]):
                     break
                 waiting.pop(0)
-                is_large = sp.L * sp.L >= self.large_sites
-                a = self._admit(sp, s_large if is_large else s_small, now)
+                lane = self.lane_of(sp.L)
+                a = self._admit(sp, streams[lane], now)
                 used += fp
-                (large if is_large else new_small).append(a)
-            # small jobs: all their sweeps in one shared launch per sweep count
-            if new_small:
+                (large if lane == 2 else new[lane]).append(a)
+            # small and medium jobs: all their sweeps in one launch per lane and sweep count
+            for lane in (0, 1):
                 by_len = {}
-                for a in new_small:
+                for a in new[lane]:
                     by_len.setdefault(a.remaining, []).append(a)
                 for n_sw, group in by_len.items():
                     if n_sw > 0:
                         api.run_many([a.job for a in group], n_sw)
                     for a in group:
                         a.remaining = 0
-                    self._finish(group, s_small, finishing)
+                    self._finish(group, streams[lane], finishing)
             # large jobs: the next block when fewer than max_inflight are outstanding
             inflight = [ev for ev in inflight if not ev.query()]
             if large and len(inflight) < self.max_inflight:
@@ -175,11 +182,11 @@ class Server:
                 ended = [a for a in large if a.remaining == 0]
                 large = [a for a in large if a.remaining > 0]
                 if ended:
-                    inflight.append(self._finish(ended, s_large, finishing))
+                    inflight.append(self._finish(ended, streams[2], finishing))
                 else:
-                    with torch.cuda.stream(s_large):
+                    with torch.cuda.stream(streams[2]):
                         ev = torch.cuda.Event()
-                        ev.record(s_large)
+                        ev.record(streams[2])
                     inflight.append(ev)
             # completions
             done = []
@@ -196,7 +203,7 @@ class Server:
                     done.append(a)
             if done:
                 finishing = [a for a in finishing if a not in done]
-            if not done and not new_small:
+            if not done and not new[0] and not new[1]:
                 if finishing or inflight:
                     time.sleep(0.0001)
                 elif pending and not waiting:

@@ -1,6 +1,6 @@
 """Serving: every job's chains are identical whether it runs alone, in the
-continuous-batching server next to other jobs (small jobs in one launch on one
-stream, large jobs in blocks on another), or in the plain one-chain-per-launch
+continuous-batching server next to other jobs (small and medium jobs in one
+launch each on their streams, large jobs in blocks on a third), or in the plain one-chain-per-launch
 form; admission respects the HBM budget."""
 import numpy as np
 import pytest
@@ -42,9 +42,11 @@ def _alone(api, serve, sp):
 def test_served_results_equal_alone(mods, budget):
     api, serve = mods
     specs = _specs()
-    # L >= 32 counts as large here, so both the one-launch small path and the
-    # blocked large path (two streams) serve part of the stream
-    srv = serve.Server(budget_bytes=budget, large_block=4, large_sites=32 * 32, keep_state=True)
+    # L = 16 is medium and L >= 32 large here, so every lane (the one-launch
+    # small and medium paths, the blocked large path) serves part of the stream
+    srv = serve.Server(budget_bytes=budget, large_block=4, medium_sites=16 * 16, large_sites=32 * 32,
+                       keep_state=True)
+    assert {srv.lane_of(sp.L) for sp in specs} == {0, 1, 2}
     res = {r.job_id: r for r in srv.run(specs)}
     assert sorted(res) == [s.job_id for s in specs]
     for sp in specs:
