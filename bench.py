@@ -42,14 +42,25 @@ PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 KERNEL_SOURCES = ("paper_2008_05401_amd/csrc/sweep_ising_impl.h", "paper_2008_05401_amd/csrc/sweep_ising_launch.h",
                   "paper_2008_05401_amd/csrc/sweep_ising_k8l5.hip", "paper_2008_05401_amd/csrc/sweep_ising.h",
                   "paper_2008_05401_amd/csrc/device_common.h", "paper_2008_05401_amd/csrc/sweep_common.h")
-MEASURED_TRAFFIC = {"sources_sha256": None, "chains": 4096, "L": 64,
-                    "fetch_scale": 2.0, "write_scale": 1.0,
-                    # sweeps per launch -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-                    "per_launch_kib": {}}
+MEASURED_TRAFFIC = {"sources_sha256": "eeb102db0e0d5894524de990dbe8ed293b7a8244d86d57d1dc44a1937f3375d3",
+                    "chains": 4096, "L": 64, "fetch_scale": 2.0, "write_scale": 1.0,
+                    # sweeps per launch -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch, mean of two launches
+                    "per_launch_kib": {20: (9415.3, 23265.5), 100: (9657.9, 24142.3)},
+                    "source": "profiles/sweep_ising_L64_batched_hbm_counters.md"}
 
-# VALU issue of the same kernel from SQ counters (rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU
-# SQ_BUSY_CYCLES ...), reported while the kernel sources hash to the measured ones
-MEASURED_VALU = {"sources_sha256": None}
+# VALU issue of the same kernel from SQ counters (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU,
+# GRBM_GUI_ACTIVE ...; two launches per length), reported while the kernel sources
+# hash to the measured ones.  Issue slots: 256 CUs x 4 SIMDs x cycles / 4 (one wave64
+# VALU instruction per four cycles per SIMD).
+MEASURED_VALU = {"sources_sha256": "eeb102db0e0d5894524de990dbe8ed293b7a8244d86d57d1dc44a1937f3375d3",
+                 "by_sweeps_per_launch": {
+                     20: {"valu_issue_fraction": 1.0768, "valu_insts_per_site_sweep": 7.770,
+                          "lanes_active": 0.9693, "lds_insts_per_site_sweep": 1.625,
+                          "salu_insts_per_site_sweep": 1.419, "lds_bank_conflicts_per_access": 0.00116},
+                     100: {"valu_issue_fraction": 1.0961, "valu_insts_per_site_sweep": 7.747,
+                           "lanes_active": 0.9699, "lds_insts_per_site_sweep": 1.623,
+                           "salu_insts_per_site_sweep": 1.406, "lds_bank_conflicts_per_access": 0.00099}},
+                 "source": "profiles/sweep_ising_L64_batched_sq_counters.md"}
 
 
 def kernel_sources_sha256():
@@ -704,9 +715,10 @@ def main():
     value = site_sweeps / wall
     acc = float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
     valu = None
-    if kernel_sources_sha256() == MEASURED_VALU["sources_sha256"]:
-        valu = {k: v for k, v in MEASURED_VALU.items() if k != "sources_sha256"}
-        valu["source"] = "profiles/sweep_ising_L64_batched_sq_counters.md"
+    if kernel_sources_sha256() == MEASURED_VALU["sources_sha256"] and (n, L) == (4096, 64):
+        v = MEASURED_VALU["by_sweeps_per_launch"].get(sweeps_per_launch)
+        if v is not None:
+            valu = dict(v, sweeps_per_launch=sweeps_per_launch, source=MEASURED_VALU["source"])
     out = {
         "metric": "MH-accepted CRBM sweeps·sites/sec on 1 GPU",
         "value": value,
@@ -751,6 +763,16 @@ def main():
     # the binding resource: VALU issue slots (one wave64 instruction per 4 cycles per SIMD)
     out["valu_issue"] = valu
     if not args.no_extra:
+        # the timed sweeps start from a random state, so "acceptance" above is a
+        # transient at short runs; the same chains after a long burn-in give the
+        # steady-state rate of the batched workload
+        burn, over = 3000, 1000
+        run(burn)
+        s0 = job.stats()
+        run(over)
+        s1 = job.stats()
+        out["acceptance_steady"] = {"value": float((s1["n_acc"].sum() - s0["n_acc"].sum()) / (n * over)),
+                                    "after_sweeps": args.warmup + args.steps + burn, "over_sweeps": over}
         out["kitaev"] = kitaev()
         out["autocorrelation"] = autocorrelation_times()
         out["frbm"] = frbm()
