@@ -490,9 +490,13 @@ def autocorrelation_times(sizes=(16, 32, 64, 128), chains=64, burn=1000, record=
     return out
 
 
-def training_and_transfer(epochs=20, lr=1e-2):
-    """Gradient of F at B=1024 Ising states (L=16, T=2.3), a short Alg. 1 training
-    run, and sampling at L=128 with 2048 chains using the trained filters."""
+def training_and_transfer(epochs=100, lr=1e-3):
+    """Gradient of F at B=1024 Ising states (L=16, T=2.3), an Alg. 1 training run
+    (ADAM at the paper's learning rate 1e-3, batch 20, ub = 200), and sampling
+    at L=128 with 2048 chains using the trained filters.  Reported: the loss of
+    Eq. (loss) over x_phys U x_RBM (the quantity Alg. 1 minimises) for the
+    initial and the trained parameters, on the final buffer, and over the
+    physical states alone."""
     import torch
 
     from paper_2008_05401_amd import api, train
@@ -507,10 +511,14 @@ def training_and_transfer(epochs=20, lr=1e-2):
     z1 = torch.zeros(1, device="cuda")
     loss0 = train.full_loss(x, E, T, p0.W, p0.hbias, z1)
     t0 = time.perf_counter()
-    r = train.train(x, E, T, epochs=epochs, batch=20, ub=200, lr=lr, seed=0)
+    r = train.train(x, E, T, epochs=epochs, batch=20, ub=200, lr=lr, seed=0, track=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     loss1 = train.full_loss(x, E, T, r.W, r.hbias, r.vbias)
+    nlp = E.to(torch.float64) / T
+    u0 = train.union_loss(r, x, nlp, p0.W, p0.hbias, z1)
+    u1 = train.union_loss(r, x, nlp, r.W, r.hbias, r.vbias)
+    h = r.history
     job = api.Job(api.CRBMParams(r.W, r.hbias, r.vbias), api.ISING, 128, np.full(2048, T), seed=1)
     job.run(5)
     sw = 20
@@ -520,7 +528,10 @@ def training_and_transfer(epochs=20, lr=1e-2):
         "grad_ms_B1024_L16": grad_ms, "free_energy_ms_B1024_L16": fwd_ms,
         "exact_sample_acceptance": acc0, "train_epochs": epochs, "train_steps": r.steps, "train_s": train_s,
         "adam_lr": lr, "minibatch": 20, "replay_update": 200,
-        "loss_init": loss0, "loss_trained": loss1,
+        "loss_phys_init": loss0, "loss_phys_trained": loss1,
+        "loss_union_init": u0, "loss_union_trained": u1,
+        "loss_union_by_epoch": [round(e["loss_tot_after"], 3) for e in h[::10]] + [round(h[-1]["loss_tot_after"], 3)],
+        "epochs_lowering_their_loss": sum(e["loss_tot_after"] < e["loss_tot_before"] for e in h),
         "transfer_L128_chains2048_site_sweeps_per_s": 2048 * 128 * 128 * sw / (ms * 1e-3),
         "transfer_acceptance": float(st["n_acc"].sum() / st["sweeps"].sum())}
 
@@ -528,8 +539,9 @@ def training_and_transfer(epochs=20, lr=1e-2):
 def kitaev_training_and_transfer(L=6, L_big=12, T=0.3):
     """Sec. IV: a Kitaev CRBM (K=8, C=3, 3x3) pre-trained on random gauge
     configurations at L=6, finished on samples it drew itself (persistent
-    replicas), then used at L=12 (128 chains): exchange acceptance of the
-    initial, pre-trained and trained filters with the refreshed replica."""
+    replicas; Alg. 1 with the replay buffer, the parameters of the epoch with
+    the lowest loss kept), then used at L=12 (128 chains): exchange acceptance
+    of the initial, pre-trained and trained filters with the refreshed replica."""
     import torch
 
     from paper_2008_05401_amd import api, train, workloads as WL
@@ -548,7 +560,13 @@ def kitaev_training_and_transfer(L=6, L_big=12, T=0.3):
                                   "pretrained": train.full_loss_nlp(xr, nr, pre.W, pre.hbias, pre.vbias)},
            "loss_self_samples": {"initial": train.full_loss_nlp(x, nx, W0, z8, z3),
                                  "pretrained": train.full_loss_nlp(x, nx, pre.W, pre.hbias, pre.vbias),
-                                 "trained": train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)}}
+                                 "trained": train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)},
+           # the quantity Alg. 1 minimises, over x_phys U x_RBM with the final buffer
+           "loss_union": {"initial": train.union_loss(fin, x, nx, W0, z8, z3),
+                          "pretrained": train.union_loss(fin, x, nx, pre.W, pre.hbias, pre.vbias),
+                          "trained": train.union_loss(fin, x, nx, fin.W, fin.hbias, fin.vbias)},
+           "fine_training_loss_by_epoch": [round(e["loss_tot_after"], 4) for e in fin.history],
+           "fine_training_best_epoch": fin.best_epoch}
     for name, (W, hb, vb) in (("initial", (f0.W, f0.hbias, f0.vbias)), ("pretrained", (pre.W, pre.hbias, pre.vbias)),
                               ("trained", (fin.W, fin.hbias, fin.vbias))):
         job = api.Job(api.CRBMParams(W, hb, vb), api.KITAEV, L_big, np.full(128, T), seed=5)

@@ -7,9 +7,12 @@ lattice, on the GPU, for the Ising and the Kitaev targets.
   minimised with ADAM; F and its gradient run in the HIP kernels through
   `api.CRBMFreeEnergy` (forward `crbm_free_energy`, backward `crbm_grad`).
 * Parameters initialised as in Alg. 1: W ~ N(0, 2/(K Lw^2)), biases 0.
-* Replay buffer of RBM samples (Alg. 1): `ub` new states per epoch from plain
-  block-Gibbs chains of the current CRBM (target CRBM_GIBBS), the oldest
-  states dropped beyond the train size; their nlp is evaluated on the GPU.
+* Replay buffer of RBM samples (Alg. 1): `ub` persistent block-Gibbs chains
+  of the current CRBM (target CRBM_GIBBS) started from Binomial(p = 0.5)
+  states; each buffer update advances them by k Gibbs steps and puts them in
+  front of x_RBM, the oldest states dropped beyond the train size N; the
+  buffer is filled to N before training; the nlp of new states is evaluated on
+  the GPU.
 * Physical training states:
   - Ising: independent chains of the exact sampler (the App. C kernel of the
     target temperature plus the MH correction), so no local Metropolis run is
@@ -66,6 +69,16 @@ class TrainResult:
     vbias: torch.Tensor
     losses: list
     steps: int
+    # the replay buffer x_RBM at the end and its -log P_phys (None without replay)
+    x_rbm: torch.Tensor = None
+    nlp_rbm: torch.Tensor = None
+    # per epoch (with track=True): the loss of Eq. (loss) with its optimal C over
+    # the epoch's training set x_tot = x_phys U x_RBM before and after the epoch's
+    # steps, and after them over x_phys and over x_RBM alone; "offset" is the mean
+    # of E beta - F over x_RBM minus that over x_phys (after the steps)
+    history: list = None
+    # with keep_best: the epoch whose parameters are returned
+    best_epoch: int = None
 
 
 def _params_of(f, dev):
@@ -73,15 +86,28 @@ def _params_of(f, dev):
             torch.tensor(f.vbias, device=dev, requires_grad=True))
 
 
+def _loss_over(x, nlp, W, hb, vb, open_cols):
+    with torch.no_grad():
+        F = api.crbm_free_energy_fn(x, W, hb, vb, open_cols)
+        d = nlp - F
+        return float(((d - d.mean()) ** 2).mean()), float(d.mean())
+
+
 def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K: int = 8, Lw: int = 5,
                epochs: int = 30, batch: int = 20, lr: float = 1e-3, ub: int = 200, gibbs_k: int = 1, seed: int = 0,
                train_size: int = None, log_every: int = 0, init=None, replay: bool = True,
-               open_cols=None) -> TrainResult:
+               open_cols=None, track: bool = False, keep_best: bool = False) -> TrainResult:
     """Alg. 1 on physical states x_phys [n][C][L][L] with nlp_phys = -log P(x_phys) + const.
     `nlp_fn(x)` evaluates the same for replay-buffer states; `init` optionally
     continues from filters (W, hbias, vbias) instead of the Alg. 1 initialisation
     (filter banks of a locally connected CRBM included; open_cols as in
-    api.CRBMParams)."""
+    api.CRBMParams).  The buffer x_RBM is filled to the train size N before the
+    first epoch (Alg. 1 iterates UPDATE BUFFER until its size is N); every epoch
+    then runs UPDATE BUFFER once and one pass of minibatches over x_phys U x_RBM.
+    Training stops when the loss no longer decreases (App. D); with keep_best the
+    parameters returned are those of the epoch whose loss over its x_tot, after
+    its steps, was lowest (ADAM at batch 20 leaves the loss fluctuating around
+    its floor from epoch to epoch)."""
     dev = x_phys.device
     C = int(x_phys.shape[1])
     L = int(x_phys.shape[-1])
@@ -94,27 +120,42 @@ def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K
     N = train_size or int(x_phys.shape[0])
     gen = torch.Generator(device="cpu").manual_seed(seed)
     nlp_phys = nlp_phys.to(device=dev, dtype=torch.float64)
+    xb = nb = None
     if replay:
-        # buffer starts from Binomial(p = 0.5) states (Alg. 1)
-        buf = torch.from_numpy(workloads.random_states(ub, C, L, seed=seed + 1)).to(dev)
-        xb = buf.clone()
-        nb = nlp_fn(xb)
+        # x-bar_RBM starts from Binomial(p = 0.5) states (Alg. 1)
+        chains = torch.from_numpy(workloads.random_states(ub, C, L, seed=seed + 1)).to(dev)
+        xb = chains[:0]
+        nb = torch.zeros(0, dtype=torch.float64, device=dev)
+        n_upd = 0
+
+        def update_buffer():
+            # UPDATE BUFFER: k Gibbs steps of the current CRBM on x-bar_RBM, which joins
+            # x_RBM in front; the oldest states beyond N are removed
+            nonlocal chains, xb, nb, n_upd
+            p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev, open_cols=open_cols)
+            job = api.Job(p, api.GIBBS, L, np.full(ub, T), seed=seed + 1000 + n_upd, gibbs_k=gibbs_k, state=chains)
+            job.run(1)
+            chains = job.state.clone()
+            job.close()
+            n_upd += 1
+            xb = torch.cat([chains, xb])[:N]
+            nb = torch.cat([nlp_fn(chains).to(torch.float64), nb])[:N]
+
+        while xb.shape[0] < N:
+            update_buffer()
     losses = []
+    history = [] if track else None
+    best = None
     steps = 0
     for ep in range(epochs):
         if replay:
-            # UPDATE BUFFER: k Gibbs steps of the current CRBM from the previous new states
-            p = api.CRBMParams(W.detach(), hb.detach(), vb.detach(), device=dev, open_cols=open_cols)
-            job = api.Job(p, api.GIBBS, L, np.full(ub, T), seed=seed + 1000 + ep, gibbs_k=gibbs_k, state=buf)
-            job.run(1)
-            buf = job.state.clone()
-            job.close()
-            xb = torch.cat([buf, xb])[:N]
-            nb = torch.cat([nlp_fn(buf), nb])[:N]
+            update_buffer()
             x_tot = torch.cat([x_phys, xb])
-            n_tot = torch.cat([nlp_phys, nb.to(torch.float64)])
+            n_tot = torch.cat([nlp_phys, nb])
         else:
             x_tot, n_tot = x_phys, nlp_phys
+        if track:
+            before, _ = _loss_over(x_tot, n_tot, W, hb, vb, open_cols)
         perm = torch.randperm(x_tot.shape[0], generator=gen).to(dev)
         for s0 in range(0, x_tot.shape[0] - batch + 1, batch):
             idx = perm[s0:s0 + batch]
@@ -127,7 +168,20 @@ def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K
             opt.step()
             steps += 1
             losses.append(float(loss.detach()) if (log_every and steps % log_every == 0) else math.nan)
-    return TrainResult(W.detach().clone(), hb.detach().clone(), vb.detach().clone(), losses, steps)
+        if track or keep_best:
+            after, _ = _loss_over(x_tot, n_tot, W, hb, vb, open_cols)
+            if keep_best and (best is None or after < best[0]):
+                best = (after, ep, W.detach().clone(), hb.detach().clone(), vb.detach().clone())
+        if track:
+            lp, cp = _loss_over(x_phys, nlp_phys, W, hb, vb, open_cols)
+            h = {"epoch": ep, "steps": steps, "loss_tot_before": before, "loss_tot_after": after, "loss_phys": lp}
+            if replay:
+                lr_, cr = _loss_over(xb, nb, W, hb, vb, open_cols)
+                h.update(loss_rbm=lr_, offset=cr - cp)
+            history.append(h)
+    if best is not None:
+        return TrainResult(best[2], best[3], best[4], losses, steps, xb, nb, history, best_epoch=best[1])
+    return TrainResult(W.detach().clone(), hb.detach().clone(), vb.detach().clone(), losses, steps, xb, nb, history)
 
 
 def train(x_phys: torch.Tensor, E_phys: torch.Tensor, T: float, **kw) -> TrainResult:
@@ -146,6 +200,15 @@ def full_loss_nlp(x: torch.Tensor, nlp: torch.Tensor, W, hb, vb, open_cols=None)
     F = api.free_energy(p, x)
     diff = nlp.to(torch.float64) - F
     return float(((diff - diff.mean()) ** 2).mean())
+
+
+def union_loss(res: TrainResult, x_phys: torch.Tensor, nlp_phys: torch.Tensor, W, hb, vb, open_cols=None) -> float:
+    """The quantity Alg. 1 minimises: the loss of Eq. (loss), optimal C, over
+    x_phys U x_RBM with the replay buffer x_RBM that `res` ended with, for the
+    parameters (W, hb, vb)."""
+    x = torch.cat([x_phys, res.x_rbm])
+    nlp = torch.cat([nlp_phys.to(torch.float64), res.nlp_rbm.to(torch.float64)])
+    return full_loss_nlp(x, nlp, W, hb, vb, open_cols)
 
 
 def kitaev_pretrain_and_train(L: int, T: float, K: int = 8, Lw: int = 3, n_random: int = 4096, n_phys: int = 512,
@@ -172,7 +235,7 @@ def kitaev_pretrain_and_train(L: int, T: float, K: int = 8, Lw: int = 3, n_rando
     acc = float(st["n_acc"].sum() / max(1, st["sweeps"].sum()))
     job.close()
     fin = train_crbm(x, nlp(x), nlp, T, K=K, Lw=Lw, epochs=epochs, batch=20, lr=lr, ub=128, seed=seed + 1,
-                     init=(pre.W, pre.hbias, pre.vbias))
+                     init=(pre.W, pre.hbias, pre.vbias), track=True, keep_best=True)
     return pre, fin, x, acc, xr
 
 
@@ -211,5 +274,5 @@ def kitaev_open_transfer(periodic: TrainResult, L: int, T: float, n_edge: int = 
     x, _ = sample_states(p, api.KITAEV, L, T, n_phys, sweeps, seed + 21, J=J, boundary=1)
     nlp = kitaev_nlp(T, J, boundary=1)
     fin = train_crbm(x, nlp(x), nlp, T, K=int(W0.shape[1]), Lw=int(W0.shape[-1]), epochs=epochs, batch=20, lr=lr,
-                     ub=128, seed=seed + 3, init=(W0, hb0, vb0))
+                     ub=128, seed=seed + 3, init=(W0, hb0, vb0), track=True, keep_best=True)
     return init, fin, x

@@ -53,25 +53,34 @@ def test_autograd_loss_gradient_matches_oracle(mods, orc):
 
 
 def test_training_reduces_loss_and_transfers(mods):
+    # Alg. 1 at the paper's ADAM learning rate 1e-3 and batch 20 (App. D); the
+    # quantity it minimises is the loss of Eq. (loss) over x_phys U x_RBM
     api, train = mods
     L, T = 16, 2.3
     x, E, acc = train.exact_ising_samples(L, T, 256, sweeps=200, seed=0)
     assert acc > 0.9
-    # learning rate 2e-2 (the paper's 1e-3 needs thousands of steps to reach |W| ~ 2.7)
-    r = train.train(x, E, T, epochs=10, batch=20, ub=64, lr=2e-2, seed=0)
+    r = train.train(x, E, T, epochs=100, batch=20, ub=64, lr=1e-3, seed=0, track=True)
+    assert r.steps == 100 * (2 * 256 // 20) and r.x_rbm.shape[0] == 256
     f0 = WL.alg1_init_filters(8, 5, seed=0)
     W0 = torch.tensor(f0.W, device="cuda")
     z = torch.zeros(8, device="cuda")
-    l0 = train.full_loss(x, E, T, W0, z, torch.zeros(1, device="cuda"))
-    l1 = train.full_loss(x, E, T, r.W, r.hbias, r.vbias)
-    assert l1 < 0.5 * l0, (l0, l1)
+    z1 = torch.zeros(1, device="cuda")
+    nlp = E.to(torch.float64) / T
+    l0 = train.union_loss(r, x, nlp, W0, z, z1)
+    l1 = train.union_loss(r, x, nlp, r.W, r.hbias, r.vbias)
+    print("ising union loss", l0, "->", l1, "history", r.history[0], r.history[-1])
+    assert l1 < 0.3 * l0, (l0, l1)
+    h = r.history
+    assert h[-1]["loss_tot_after"] < 0.2 * h[0]["loss_tot_before"], (h[0], h[-1])
+    # most epochs lower the loss over their own training set
+    assert sum(e["loss_tot_after"] < e["loss_tot_before"] for e in h) >= 0.6 * len(h)
     # transfer: the trained filters propose better L=64 moves than the initial ones
     def acceptance(W, hb, vb):
         job = api.Job(api.CRBMParams(W, hb, vb), api.ISING, 64, np.full(64, T), seed=5)
         job.run(30)
         st = job.stats()
         return st["n_acc"].sum() / st["sweeps"].sum()
-    assert acceptance(r.W, r.hbias, r.vbias) >= acceptance(W0, z, torch.zeros(1, device="cuda"))
+    assert acceptance(r.W, r.hbias, r.vbias) >= acceptance(W0, z, z1)
 
 
 def test_kitaev_pretraining_and_self_samples(mods):
@@ -87,16 +96,29 @@ def test_kitaev_pretraining_and_self_samples(mods):
     f0 = WL.alg1_init_filters(8, 3, seed=0, C=3)
     W0 = torch.tensor(f0.W, device="cuda")
     z8, z3 = torch.zeros(8, device="cuda"), torch.zeros(3, device="cuda")
+    # pre-training has no replay buffer: its training set is the random states
     nr = nlp(xr)
     l0_r = train.full_loss_nlp(xr, nr, W0, z8, z3)
     lp_r = train.full_loss_nlp(xr, nr, pre.W, pre.hbias, pre.vbias)
     assert lp_r < 0.9 * l0_r, (l0_r, lp_r)
     nx = nlp(x)
-    lp_x = train.full_loss_nlp(x, nx, pre.W, pre.hbias, pre.vbias)
-    lf_x = train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)
-    assert np.isfinite(lf_x) and lf_x < 1.1 * lp_x, (lp_x, lf_x)
+    # Alg. 1 from its own initialisation on the self-samples: the loss over
+    # x_phys U x_RBM falls
+    r0 = train.train_crbm(x, nx, nlp, T, K=8, Lw=3, epochs=30, batch=20, lr=1e-3, ub=128, seed=3, track=True)
+    u0 = train.union_loss(r0, x, nx, W0, z8, z3)
+    u1 = train.union_loss(r0, x, nx, r0.W, r0.hbias, r0.vbias)
+    print("kitaev union loss from init", u0, "->", u1, [round(e["loss_tot_after"], 4) for e in r0.history])
+    assert u1 < 0.9 * u0, (u0, u1)
+    # fine-training from the pre-trained filters: the epoch with the lowest loss
+    # over its training set is returned, no worse than the pre-trained filters
+    # on the final x_phys U x_RBM beyond the epoch-to-epoch spread of ADAM
+    assert fin.best_epoch is not None and len(fin.history) == 6
+    up = train.union_loss(fin, x, nx, pre.W, pre.hbias, pre.vbias)
+    uf = train.union_loss(fin, x, nx, fin.W, fin.hbias, fin.vbias)
+    print("kitaev fine-training union loss", up, "->", uf, "best epoch", fin.best_epoch)
+    assert np.isfinite(uf) and uf < 1.05 * up, (up, uf)
     # the replay buffer ran three-channel Gibbs-only chains
-    assert fin.W.shape == (8, 3, 3, 3)
+    assert fin.W.shape == (8, 3, 3, 3) and fin.x_rbm.shape == (256, 3, L, L)
 
 
 def test_lcrbm_open_boundary_transfer(mods):
@@ -112,8 +134,9 @@ def test_lcrbm_open_boundary_transfer(mods):
     assert torch.equal(init.W[3], pre.W) and torch.equal(init.hbias[4], pre.hbias)
     nlp = train.kitaev_nlp(T, boundary=1)
     nx = nlp(x)
-    l0 = train.full_loss_nlp(x, nx, init.W, init.hbias, init.vbias)
-    l1 = train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)
-    assert np.isfinite(l1) and l1 < 1.1 * l0, (l0, l1)
+    l0 = train.union_loss(fin, x, nx, init.W, init.hbias, init.vbias)
+    l1 = train.union_loss(fin, x, nx, fin.W, fin.hbias, fin.vbias)
+    print("lcrbm union loss", l0, "->", l1, "best epoch", fin.best_epoch)
+    assert np.isfinite(l1) and l1 < 1.05 * l0, (l0, l1)
     # the edge banks moved away from the bulk bank during retraining
     assert not torch.equal(fin.W[1], fin.W[0])
