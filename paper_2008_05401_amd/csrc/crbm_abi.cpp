@@ -130,8 +130,9 @@ crbm_status plan_job(const crbm_params* p, const crbm_batch_desc* d, Plan* out)
         pl.nt = (d->L * d->L * std::max(p->K, p->C) >= 4 * 256) ? 256 : 64;
         // the Kitaev eigen-step is latency-bound: up to N = 64 four waves per chain (one
         // wave tridiagonalises without workgroup barriers, all four bracket the
-        // eigenvalues), one 16-wave workgroup per chain beyond
-        if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = d->L <= 8 ? 256 : 1024;
+        // eigenvalues); up to L = 12 eight waves (as fast as sixteen there, with 256
+        // VGPRs instead of spilling at 128), sixteen beyond
+        if (d->target == CRBM_KITAEV && d->L >= 4) pl.nt = d->L <= 8 ? 256 : (d->L <= 12 ? 512 : 1024);
         pl.lds = generic_lds_bytes(p->K, p->C, p->Lw, d->L, d->target, banks_of(p), p->dense);
     }
     if (pl.lds > kLdsLimit)
