@@ -508,24 +508,64 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
         for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : col(i, k);
         __syncthreads();
-        // p = bet * A22 v; row i: lower part A[i][j], j <= i (contiguous), upper part A[j][i], j > i
-        for (int i = k + 1 + grp; i < N; i += ngrp) {
-            const int rb = tri(i, 0);
-            double a0 = 0.0, a1 = 0.0;
-            int j = k + 1 + gl;
-            for (; j + G <= i; j += 2 * G) {
-                a0 += A[rb + j] * hv[j];
-                a1 += A[rb + j + G] * hv[j + G];
+        // p = bet * A22 v.  Lane gl of a G-lane group takes the columns
+        // j = k + 1 + gl + G m of every row, so it loads its v_j once per step into
+        // registers; row i reads A[i][j] from the lower triangle (j <= i, contiguous)
+        // or its mirror A[j][i], all loads of a row issued before the first product,
+        // two rows per group in flight
+        {
+            // columns j >= N read the valid entry of column N - 1 and meet v_j = 0 (A is
+            // finite), so every load is unconditional; the offsets j and j (j + 1) / 2
+            // of the lane's columns are fixed for the step
+            constexpr int MV = (KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L + G - 1) / G;
+            double hr[MV];
+            int jc[MV], tj[MV];
+#pragma unroll
+            for (int m = 0; m < MV; ++m) {
+                const int j = k + 1 + gl + G * m;
+                jc[m] = j < N ? j : N - 1;
+                tj[m] = tri(jc[m], 0);
+                const double h = hv[jc[m]];
+                hr[m] = j < N ? h : 0.0;
             }
-            if (j <= i) a0 += A[rb + j] * hv[j];
-            j = i + 1 + gl;
-            for (; j + G < N; j += 2 * G) {
-                a0 += A[tri(j, i)] * hv[j];
-                a1 += A[tri(j + G, i)] * hv[j + G];
+            auto row_dot = [&](int i, double (&t)[MV]) {
+                const int rb = tri(i, 0);
+#pragma unroll
+                for (int m = 0; m < MV; ++m) t[m] = A[jc[m] <= i ? rb + jc[m] : tj[m] + i];
+            };
+            int i = k + 1 + grp;
+            for (; i + ngrp < N; i += 2 * ngrp) {
+                double t0[MV], t1[MV];
+                row_dot(i, t0);
+                row_dot(i + ngrp, t1);
+                double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+                for (int m = 0; m < MV; m += 2) {
+                    a0 = fma(t0[m], hr[m], a0);
+                    b0 = fma(t1[m], hr[m], b0);
+                    if (m + 1 < MV) {
+                        a1 = fma(t0[m + 1], hr[m + 1], a1);
+                        b1 = fma(t1[m + 1], hr[m + 1], b1);
+                    }
+                }
+                const double acc0 = row16_sum(a0 + a1), acc1 = row16_sum(b0 + b1);
+                if (gl == 0) {
+                    p[i] = bet * acc0;
+                    p[i + ngrp] = bet * acc1;
+                }
             }
-            if (j < N) a0 += A[tri(j, i)] * hv[j];
-            const double acc = row16_sum(a0 + a1);
-            if (gl == 0) p[i] = bet * acc;
+            if (i < N) {
+                double t0[MV];
+                row_dot(i, t0);
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int m = 0; m < MV; m += 2) {
+                    a0 = fma(t0[m], hr[m], a0);
+                    if (m + 1 < MV) a1 = fma(t0[m + 1], hr[m + 1], a1);
+                }
+                const double acc0 = row16_sum(a0 + a1);
+                if (gl == 0) p[i] = bet * acc0;
+            }
         }
         __syncthreads();
         double pv = 0.0;
@@ -542,7 +582,37 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
                 pj[c] = j < N ? p[j] : 0.0;
                 vj[c] = j < N ? hv[j] : 0.0;
             }
-            for (int i = k + 1 + wid; i < N; i += nw) {
+            // four rows per wave and pass: their loads are issued together
+            int i = k + 1 + wid;
+            for (; i + 3 * nw < N; i += 4 * nw) {
+                double vi[4], ci[4], a[4][3];
+                int rb[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ii = i + r * nw;
+                    rb[r] = tri(ii, 0);
+                    vi[r] = hv[ii];
+                    ci[r] = p[ii];
+                    // unconditional loads: entries j > ii (another row's, or for j >= N the
+                    // last entry of the triangle) are read, never written back
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int j = k + 1 + lane + 64 * (c0 + c);
+                        a[r][c] = A[rb[r] + (j < N ? j : N - 1)];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ii = i + r * nw;
+                    const double cr = ci[r] - kk2 * vi[r];  // p_i - 2 kk v_i
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int j = k + 1 + lane + 64 * (c0 + c);
+                        if (j <= ii) A[rb[r] + j] = a[r][c] - (vi[r] * pj[c] + cr * vj[c]);
+                    }
+                }
+            }
+            for (; i < N; i += nw) {
                 const int rb = tri(i, 0);
                 const double vi = hv[i], pi = p[i];
                 const double ci = pi - kk2 * vi;  // p_i - 2 kk v_i
