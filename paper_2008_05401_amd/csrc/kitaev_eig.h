@@ -175,7 +175,11 @@ __device__ __forceinline__ int a_at(int i, int j, int N)
 // over), lane `sub` of the group evaluating the point lo + (sub + 1) h,
 // h = (hi - lo) / (G + 1), so the bracket shrinks (G + 1)-fold per step; the
 // group finds its first point whose count exceeds the eigenvalue's index from
-// a ballot.  The count comes from the division-free three-term recurrence
+// a ballot.  Once a group's bracket holds its eigenvalue alone, the points
+// cluster around the secant root of p_N between the bracket's ends instead
+// (regula falsi on the determinant, every bracket still certified by counts),
+// which ends in a few steps what multisection would take some twenty for.
+// The count comes from the division-free three-term recurrence
 // p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, p_i = det(T_i - x), one
 // eigenvalue below x per sign change of p_i / p_{i-1}; an exact zero is
 // replaced by -2^-100 p_{i-1} (the sign convention of the ratio form), and the
@@ -201,20 +205,55 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
     const double scale = fmax(fabs(glo), fabs(ghi));
     const int G = kitaev_group_size(N, nw), per_wave = 64 / G, cap = nw * per_wave;
     const int gi = lane / G, sub = lane - gi * G;
+    const int gbase = gi * G < 64 ? gi * G : 0;
     const unsigned long long gmask = ((1ull << G) - 1ull) << (gi * G);
     const int rounds = (N + cap - 1) / cap;
     for (int rd = 0; rd < rounds; ++rd) {
         const int idx = rd * cap + wid * per_wave + gi;
         const bool mine = gi < per_wave && idx < N;
         double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
+        // counts and scaled determinants p_N = m 2^x at the bracket's ends (ends
+        // not yet evaluated carry no determinant)
+        int clo = 0, chi = N;
+        double mlo = 0.0, mhi = 0.0;
+        int xlo = 0, xhi = 0;
+        bool flo = false, fhi = false, sec_failed = false;
+        int q = 4;  // the cluster spans w 2^-q; doubled after every hit (the secant error squares)
         bool live = mine;
         for (int it = 0; it < 256; ++it) {
-            const double h = (hi - lo) / (double)(G + 1);
-            const double x = lo + (double)(sub + 1) * h;
+            const double w = hi - lo;
+            const double h = w / (double)(G + 1);
             // done: bracket small enough, or no representable progress left
-            if (live && (!(hi - lo > tol) || !(lo + h > lo) || !(lo + (double)G * h < hi))) live = false;
+            if (live && (!(w > tol) || !(lo + h > lo) || !(lo + (double)G * h < hi))) live = false;
             if (!__any(live)) break;
-            int cnt = 0;
+            // Point placement.  Multisection: lo + (s + 1) h.  Once the bracket holds
+            // exactly this eigenvalue (counts idx and idx + 1 at its ends, whose
+            // determinants then differ in sign) the G points go to a cluster of
+            // spacing dd = w 2^-q / (G - 1) around the secant root of the
+            // determinant; q doubles after each hit, and a cluster that misses the
+            // root is followed by one multisection step and q = 4 again.
+            bool sec = G >= 2 && flo && fhi && clo == idx && chi == idx + 1 && !sec_failed;
+            double a0 = 0.0, dd = 0.0;
+            if (sec) {
+                const int de = xlo - xhi;
+                double t;
+                if (de > 1000)
+                    t = 1.0;
+                else if (de < -1000)
+                    t = 0.0;
+                else {
+                    const double r = ldexp(mlo / mhi, de);  // p_N(lo) / p_N(hi) < 0
+                    t = r / (r - 1.0);
+                }
+                dd = ldexp(w, -q) / (double)(G - 1);
+                const double span = dd * (double)(G - 1);
+                a0 = lo + w * t - 0.5 * span;
+                a0 = fmin(fmax(a0, lo + dd), hi - span - dd);
+                sec = a0 > lo && a0 + dd > a0 && a0 + span < hi;
+            }
+            const double x = sec ? a0 + (double)sub * dd : lo + (double)(sub + 1) * h;
+            int cnt = 0, xe = 0;
+            double pm = 1.0;
             if (live) {
                 double p0 = 1.0, p1 = d[0] - x;
                 if (p1 == 0.0) p1 = -0x1p-100;
@@ -235,7 +274,9 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
                         p0 = p1;
                         p1 = pn;
                     }
-                    const double f = fabs(p1) > 0x1p+100 ? 0x1p-100 : (fabs(p1) < 0x1p-100 ? 0x1p+100 : 1.0);
+                    const bool big = fabs(p1) > 0x1p+100, small = fabs(p1) < 0x1p-100;
+                    const double f = big ? 0x1p-100 : (small ? 0x1p+100 : 1.0);
+                    xe += big ? 100 : (small ? -100 : 0);
                     p0 *= f;
                     p1 *= f;
                 }
@@ -246,14 +287,36 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
                     p0 = p1;
                     p1 = pn;
                 }
+                pm = p1;
             }
             // the group's first point with more than idx eigenvalues below it
             const unsigned long long mg = (__ballot(live && cnt > idx) & gmask) >> (gi * G);
+            const int s0 = mg ? __builtin_ctzll(mg) : G;
+            // count and determinant at the points that become the new ends
+            const int sl = gbase + (s0 > 0 ? s0 - 1 : 0), sh = gbase + (s0 < G ? s0 : G - 1);
+            const int c_l = __shfl(cnt, sl), c_h = __shfl(cnt, sh);
+            const double m_l = __shfl(pm, sl), m_h = __shfl(pm, sh);
+            const int x_l = __shfl(xe, sl), x_h = __shfl(xe, sh);
             if (live) {
-                const int s0 = mg ? __builtin_ctzll(mg) : G;
-                const double nlo = lo + (double)s0 * h;
-                hi = s0 < G ? lo + (double)(s0 + 1) * h : hi;
+                auto pt = [&](int q) { return sec ? a0 + (double)q * dd : lo + (double)(q + 1) * h; };
+                const double nlo = s0 > 0 ? pt(s0 - 1) : lo;
+                const double nhi = s0 < G ? pt(s0) : hi;
+                if (s0 > 0) {
+                    clo = c_l;
+                    mlo = m_l;
+                    xlo = x_l;
+                    flo = true;
+                }
+                if (s0 < G) {
+                    chi = c_h;
+                    mhi = m_h;
+                    xhi = x_h;
+                    fhi = true;
+                }
+                sec_failed = sec && (s0 == 0 || s0 == G);
+                if (sec) q = sec_failed ? 4 : (q < 24 ? 2 * q : 48);
                 lo = nlo;
+                hi = nhi;
             }
         }
         __syncthreads();  // every lane has read d and e2 of this round; eps may overwrite the matrix
