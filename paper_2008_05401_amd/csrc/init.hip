@@ -81,7 +81,7 @@ __global__ __launch_bounds__(BLOCK) void init_kernel(SweepLaunch P)
     } else {
         const int N = LL;
         const KitaevBufs kb = kitaev_bufs(kit, J.kitA ? J.kitA + (size_t)g * kitaev_chain_doubles(L) : nullptr, L);
-        ko = kitaev_weight_block(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], kb, red);
+        ko = kitaev_weight_block<BLOCK>(v, C, L, J.boundary, J.J0, J.J1, J.J2, 1.0 / J.T[g], kb, red);
         // singular values of the initial state, kept for temperature swaps
         if (J.eps)
             for (int q = tid; q < N; q += NT) J.eps[(size_t)g * N + q] = kb.eps[q];

@@ -745,6 +745,96 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Householder steps of kitaev_tridiag_wave with the rows in registers (NCT
+// columns, N <= NCT <= 40): lane i holds row i of the trailing matrix; at step k
+// lane k writes its row to cb (A's storage, dead once the rows are loaded), from
+// which every lane reads its entry of column k (symmetry) and the diagonal;
+// v and w go through LDS as before and are read by every lane (broadcast).
+// Lanes <= k and >= N get v_i = w_i = 0, so their rows, and the columns j <= k,
+// stay as they are.
+template <int NCT>
+__device__ __forceinline__ void kitaev_tridiag_regs(int N, int NS, int lane, lds_f64* A, lds_f64* d, lds_f64* e,
+                                                    lds_f64* vb, lds_f64* wb)
+{
+    double row[NCT];
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) row[j] = lane < N ? A[lane * NS + j] : 0.0;
+    wave_sync();
+    lds_f64* cb = A;
+    for (int k = 0; k + 2 < N; ++k) {
+        if (lane == k) {
+#pragma unroll
+            for (int j = 0; j < NCT; ++j) cb[j] = row[j];
+        }
+        wave_sync();
+        const bool act = lane < N && lane > k;
+        const double x = act ? cb[lane] : 0.0;
+        const double dk = cb[k];
+        const double x0 = cb[k + 1];
+        const double s2 = wave_sum_dpp(x * x);
+        const double rest = s2 - x0 * x0;
+        if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
+            if (lane == 0) {
+                d[k] = dk;
+                e[k] = x0;
+            }
+            wave_sync();
+            continue;
+        }
+        const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
+        const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
+        const double vi = lane == k + 1 ? x0 - alpha : x;
+        if (lane < NCT) vb[lane] = vi;
+        wave_sync();
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        // eight columns at a time: the scheduler may not hoist the loads of later
+        // chunks (their registers would push the rows out of the register file)
+#pragma unroll
+        for (int j = 0; j < NCT; j += 4) {
+            a0 = fma(row[j], vb[j], a0);
+            a1 = fma(row[j + 1], vb[j + 1], a1);
+            a2 = fma(row[j + 2], vb[j + 2], a2);
+            a3 = fma(row[j + 3], vb[j + 3], a3);
+            if ((j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
+        }
+        const double p = act ? bet * ((a0 + a1) + (a2 + a3)) : 0.0;
+        const double kk2 = bet * wave_sum_dpp(p * vi);  // 2 kk
+        const double wi = act ? p - 0.5 * kk2 * vi : 0.0;
+        if (lane < NCT) wb[lane] = wi;
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) {
+            row[j] = row[j] - (vi * wb[j] + wi * vb[j]);
+            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        if (lane == 0) {
+            d[k] = dk;
+            e[k] = alpha;
+        }
+        wave_sync();
+    }
+    // the trailing 2 x 2 block (or the single entry for N = 1)
+    if (N >= 2) {
+        if (lane == N - 2) {
+#pragma unroll
+            for (int j = 0; j < NCT; ++j) cb[j] = row[j];
+        }
+        wave_sync();
+        if (lane == 0) {
+            d[N - 2] = cb[N - 2];
+            e[N - 2] = cb[N - 1];
+        }
+        wave_sync();
+    }
+    if (lane == N - 1) {
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) cb[j] = row[j];
+    }
+    wave_sync();
+    if (lane == 0) d[N - 1] = cb[N - 1];
+    wave_sync();
+}
+
 __device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int open_cols, double Jx, double Jy,
                                                  double Jz, lds_f64* A, lds_f64* d, lds_f64* e, lds_f64* vb,
                                                  lds_f64* wb)
@@ -805,7 +895,12 @@ __device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int o
         }
     }
     wave_sync();
-    // 2. Householder: step k annihilates column k below the subdiagonal
+    // 2. Householder: step k annihilates column k below the subdiagonal; up to
+    //    40 columns (L <= 6) with the rows in registers
+    if (NC <= 8) return kitaev_tridiag_regs<8>(N, NS, lane, A, d, e, vb, wb);
+    if (NC <= 16) return kitaev_tridiag_regs<16>(N, NS, lane, A, d, e, vb, wb);
+    if (NC <= 32) return kitaev_tridiag_regs<32>(N, NS, lane, A, d, e, vb, wb);
+    if (NC <= 40) return kitaev_tridiag_regs<40>(N, NS, lane, A, d, e, vb, wb);
     lds_f64* row = A + (lane < N ? lane : 0) * NS;
     const bool own = lane < N;
     for (int k = 0; k + 2 < N; ++k) {
@@ -917,12 +1012,18 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
     return o;
 }
 
-// S, E_f, C_f of the proposal v; the eigenvalues eps_lambda go to b.eps
+// S, E_f, C_f of the proposal v; the eigenvalues eps_lambda go to b.eps.  BLOCK
+// is the caller's compile-time workgroup size: only 256-thread kernels reach the
+// four-wave path, so its out-of-line functions get the register budget of a
+// 256-thread workgroup rather than the 128 VGPRs of a 1024-thread one.
+template <int BLOCK>
 __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, int open_cols, double Jx, double Jy,
                                                 double Jz, double beta, const KitaevBufs& b, double* red)
 {
-    if (blockDim.x == KITAEV_SMALL_NT && L * L <= KITAEV_WAVE_MAX_N)
-        return kitaev_weight_small(v, C, L, open_cols, Jx, Jy, Jz, beta, b.eps, b.eps, red);
+    if constexpr (BLOCK == KITAEV_SMALL_NT) {
+        if (L * L <= KITAEV_WAVE_MAX_N)
+            return kitaev_weight_small(v, C, L, open_cols, Jx, Jy, Jz, beta, b.eps, b.eps, red);
+    }
     lds_u8c* vl = (lds_u8c*)v;
     if (kitaev_a_in_lds(L))
         return kitaev_weight_block_t<false>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (lds_f64*)b.A, (lds_f64*)b.d,

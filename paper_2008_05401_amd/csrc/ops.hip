@@ -153,9 +153,10 @@ hipError_t launch_ising_energy(const int8_t* x, int B, int L, int open_cols, int
 // ---------------------------------------------------------------------------
 // Kitaev S = sum log 2cosh(eps / 2T), FP64; one workgroup per configuration.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, int open_cols,
-                                                            double Jx, double Jy, double Jz,
-                                                            const double* __restrict__ T, double* __restrict__ S)
+template <int NT>
+__global__ __launch_bounds__(NT) void kitaev_weight_kernel(const int8_t* __restrict__ x, int C, int L, int open_cols,
+                                                          double Jx, double Jy, double Jz,
+                                                          const double* __restrict__ T, double* __restrict__ S)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = L * L;
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(1024) void kitaev_weight_kernel(const int8_t* __res
     for (int q = threadIdx.x; q < C * N; q += blockDim.x) v[q] = xs[q] > 0;
     __syncthreads();
     // the stand-alone op keeps A in LDS (L <= 12)
-    const KitaevOut o = kitaev_weight_block(v, C, L, open_cols, Jx, Jy, Jz, 1.0 / T[blockIdx.x],
-                                            kitaev_bufs(A, nullptr, L), red);
+    const KitaevOut o = kitaev_weight_block<NT>(v, C, L, open_cols, Jx, Jy, Jz, 1.0 / T[blockIdx.x],
+                                                kitaev_bufs(A, nullptr, L), red);
     if (threadIdx.x == 0) S[blockIdx.x] = o.S;
 }
 
@@ -176,8 +177,12 @@ size_t kitaev_weight_lds(int C, int L) { return 64 * 8 + kitaev_lds_bytes(L) + (
 hipError_t launch_kitaev_weight(const int8_t* x, int B, int C, int L, int open_cols, double Jx, double Jy, double Jz,
                                 const double* T, double* S, hipStream_t s)
 {
-    hipLaunchKernelGGL(kitaev_weight_kernel, dim3(B), dim3(L * L >= 16 ? 1024 : 256), kitaev_weight_lds(C, L), s, x, C, L,
-                       open_cols, Jx, Jy, Jz, T, S);
+    if (L * L >= 16)
+        hipLaunchKernelGGL(kitaev_weight_kernel<1024>, dim3(B), dim3(1024), kitaev_weight_lds(C, L), s, x, C, L,
+                           open_cols, Jx, Jy, Jz, T, S);
+    else
+        hipLaunchKernelGGL(kitaev_weight_kernel<256>, dim3(B), dim3(256), kitaev_weight_lds(C, L), s, x, C, L,
+                           open_cols, Jx, Jy, Jz, T, S);
     return hipGetLastError();
 }
 

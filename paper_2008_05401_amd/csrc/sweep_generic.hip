@@ -259,7 +259,7 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
         if (ising) ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
         else {
             const KitaevBufs kb = kitaev_bufs(kit, scratch, L);
-            ko = kitaev_weight_block(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
+            ko = kitaev_weight_block<NT>(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
         }
         double lu = 0.0;
         if (tid == 0) {
