@@ -596,6 +596,10 @@ def kitaev_open_boundary(periodic, L, T, n_edge=3):
     nx = nlp(x)
     out["loss_open_samples"] = {"initial": train.full_loss_nlp(x, nx, init.W, init.hbias, init.vbias),
                                 "retrained": train.full_loss_nlp(x, nx, fin.W, fin.hbias, fin.vbias)}
+    # the quantity Alg. 1 minimises: the loss over the samples and the final replay buffer
+    out["loss_union"] = {"initial": train.union_loss(fin, x, nx, init.W, init.hbias, init.vbias),
+                         "retrained": train.union_loss(fin, x, nx, fin.W, fin.hbias, fin.vbias),
+                         "best_epoch": fin.best_epoch}
     cases = (("periodic_crbm", api.CRBMParams(periodic.W, periodic.hbias, periodic.vbias)),
              ("lcrbm_initial", api.CRBMParams(init.W, init.hbias, init.vbias)),
              ("lcrbm_retrained", api.CRBMParams(fin.W, fin.hbias, fin.vbias)))
