@@ -40,6 +40,7 @@
 // itself by one-sided Jacobi (kitaev_weight_jacobi), which never squares M.
 #pragma once
 #include "device_common.h"
+#include <type_traits>
 
 namespace crbm {
 
@@ -421,9 +422,19 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         slot ^= 1;
         if (lane == 0) r[wid] = x;
         __syncthreads();
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += r[w];
-        return t;
+        // all sixteen slots are read at once (one LDS latency instead of nw in a
+        // row); those of absent waves are discarded by the select
+        double t[16];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const double rw = r[w];
+            t[w] = w < nw ? rw : 0.0;
+        }
+#pragma unroll
+        for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+            for (int w = 0; w < h; ++w) t[w] += t[w + h];
+        return t[0];
     };
     // column k below the diagonal: in the full form read as row k (symmetry)
     auto col = [&](int i, int k) -> double { return kFull ? A[k * N + i] : A[tri(i, k)]; };
@@ -634,57 +645,57 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         double pv = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) pv += p[i] * hv[i];
         const double kk2 = bet * reduce(pv);  // 2 kk
-        // A22 -= v p^T + p v^T - 2 kk v v^T (lower triangle); a lane keeps the
-        // column values p_j, v_j of three columns in registers per pass, a pass
-        // per 192 columns
-        for (int c0 = 0; k + 1 + 64 * c0 < N; c0 += 3) {
-            double pj[3], vj[3];
+        // A22 -= v p^T + p v^T - 2 kk v v^T on the lower triangle.  The R = N - k - 1
+        // trailing rows are paired, (k + 1 + t, N - 1 - t), so that a pair holds R + 1
+        // entries whatever t: a wave per pair, its lanes along the two row segments
+        // one after the other (the middle row of an odd R alone), so no lane is
+        // given a column beyond its row's end except in a pair's last 64-entry slot
+        {
+            // a pair's bookkeeping is wave-uniform (scalar); per lane and 64-entry slot
+            // only the column, the address and the guard of the store are computed.
+            // All slots of a pair (at most three: N <= 144 < 3 x 64) are loaded before
+            // the first store, lanes past a pair's end reading a valid entry that is
+            // not written back.
+            static_assert(KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L < 3 * 64, "a pair must fit three slots");
+            const int R = N - k - 1, npair = (R + 1) / 2;
+            const int top = N * (N + 1) / 2 - 1;
+            // slots per pair: ceil((R + 1) / 64), the same for every pair of the step
+            auto pairs = [&](auto nslot) {
+                constexpr int NSL = decltype(nslot)::value;
+                for (int t = __builtin_amdgcn_readfirstlane(wid); t < npair; t += nw) {
+                    const int ra = k + 1 + t, rz = N - 1 - t;
+                    const int la = t + 1, len = rz == ra ? la : R + 1;
+                    const int ba = tri(ra, 0) + k + 1, bz = tri(rz, 0) + k + 1 - la;
+                    const double va = hv[ra], vz = hv[rz];
+                    const double ca = p[ra] - kk2 * va, cz = p[rz] - kk2 * vz;  // p_i - 2 kk v_i
+                    double a[NSL], pj[NSL], vj[NSL];
+                    int ix[NSL];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int j = k + 1 + lane + 64 * (c0 + c);
-                pj[c] = j < N ? p[j] : 0.0;
-                vj[c] = j < N ? hv[j] : 0.0;
-            }
-            // four rows per wave and pass: their loads are issued together
-            int i = k + 1 + wid;
-            for (; i + 3 * nw < N; i += 4 * nw) {
-                double vi[4], ci[4], a[4][3];
-                int rb[4];
+                    for (int c = 0; c < NSL; ++c) {
+                        const int q = lane + 64 * c;
+                        const bool in_a = q < la;
+                        const int jj = k + 1 + (in_a ? q : q - la);
+                        const int jc = jj < N ? jj : N - 1;
+                        const int x = (in_a ? ba : bz) + q;
+                        ix[c] = x < top ? x : top;
+                        a[c] = A[ix[c]];
+                        pj[c] = p[jc];
+                        vj[c] = hv[jc];
+                    }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int ii = i + r * nw;
-                    rb[r] = tri(ii, 0);
-                    vi[r] = hv[ii];
-                    ci[r] = p[ii];
-                    // unconditional loads: entries j > ii (another row's, or for j >= N the
-                    // last entry of the triangle) are read, never written back
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int j = k + 1 + lane + 64 * (c0 + c);
-                        a[r][c] = A[rb[r] + (j < N ? j : N - 1)];
+                    for (int c = 0; c < NSL; ++c) {
+                        const int q = lane + 64 * c;
+                        const bool in_a = q < la;
+                        if (q < len) A[ix[c]] = a[c] - ((in_a ? va : vz) * pj[c] + (in_a ? ca : cz) * vj[c]);
                     }
                 }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int ii = i + r * nw;
-                    const double cr = ci[r] - kk2 * vi[r];  // p_i - 2 kk v_i
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int j = k + 1 + lane + 64 * (c0 + c);
-                        if (j <= ii) A[rb[r] + j] = a[r][c] - (vi[r] * pj[c] + cr * vj[c]);
-                    }
-                }
-            }
-            for (; i < N; i += nw) {
-                const int rb = tri(i, 0);
-                const double vi = hv[i], pi = p[i];
-                const double ci = pi - kk2 * vi;  // p_i - 2 kk v_i
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int j = k + 1 + lane + 64 * (c0 + c);
-                    if (j <= i) A[rb + j] -= vi * pj[c] + ci * vj[c];
-                }
-            }
+            };
+            if (R + 1 <= 64)
+                pairs(std::integral_constant<int, 1>{});
+            else if (R + 1 <= 128)
+                pairs(std::integral_constant<int, 2>{});
+            else
+                pairs(std::integral_constant<int, 3>{});
         }
         if (tid == 0) {
             d[k] = A[a_at<kFull>(k, k, N)];
