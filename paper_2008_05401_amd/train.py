@@ -121,6 +121,8 @@ def train_crbm(x_phys: torch.Tensor, nlp_phys: torch.Tensor, nlp_fn, T: float, K
     gen = torch.Generator(device="cpu").manual_seed(seed)
     nlp_phys = nlp_phys.to(device=dev, dtype=torch.float64)
     xb = nb = None
+    if replay and ub < 1:
+        raise ValueError(f"the buffer update size ub must be >= 1 (got {ub})")
     if replay:
         # x-bar_RBM starts from Binomial(p = 0.5) states (Alg. 1)
         chains = torch.from_numpy(workloads.random_states(ub, C, L, seed=seed + 1)).to(dev)
