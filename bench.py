@@ -100,7 +100,8 @@ def lds_table_bytes_per_site_sweep(K, C, Lw, gibbs_k=1):
 def gpu_warm(api, f, L, T, seconds, seed):
     """Bring the GPU to the clocks it holds under this kernel before the timed
     region: a throw-away job of the measured shape (another seed) runs 10-sweep
-    launches for `seconds`, ending right before the first timed launch.  The
+    launches for `seconds`, ending right before the measured job's warm-up
+    sweeps (then its timed launches).  The
     batched workload runs 10^4 sweeps, seconds of continuous sweeps, while a
     run of --steps 20 lasts 4 ms: after even 50 ms of idle the first launches
     run at lower clocks (4.6-4.8 ms for 20 sweeps instead of 3.9).  The
@@ -702,8 +703,10 @@ def main():
             job.run(b)
             done += b
 
-    run(args.warmup)
+    # clocks first, then the measured job's own warm-up sweeps, so that its state is the
+    # last data the GPU touched before the timed launches
     warm_s = gpu_warm(api, f, L, T, args.gpu_warm_ms * 1e-3, seed + 12345) if args.gpu_warm_ms > 0 else 0.0
+    run(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     launches = []
