@@ -563,9 +563,13 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         }
     } else
     for (int k = 0; k + 2 < N; ++k) {
+        // column k below the diagonal: its norm, and the entries of v except the
+        // first (v_{k+1} = x0 - alpha is formed where it is used, and stored by
+        // thread 0 before the next barrier)
         double s2 = 0.0;
         for (int i = k + 1 + tid; i < N; i += nt) {
             const double x = col(i, k);
+            hv[i] = x;
             s2 += x * x;
         }
         s2 = reduce(s2);
@@ -580,18 +584,19 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         }
         const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
         const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
-        for (int i = k + 1 + tid; i < N; i += nt) hv[i] = (i == k + 1) ? (x0 - alpha) : col(i, k);
-        __syncthreads();
-        // p = bet * A22 v.  Lane gl of a G-lane group takes the columns
+        const double v1 = x0 - alpha;
+        if (tid == 0) hv[k + 1] = v1;
+        // p = bet * A22 v and p.v.  Lane gl of a G-lane group takes the columns
         // j = k + 1 + gl + G m of every row, so it loads its v_j once per step into
         // registers; row i reads A[i][j] from the lower triangle (j <= i, contiguous)
         // or its mirror A[j][i], all loads of a row issued before the first product,
-        // two rows per group in flight
-        {
-            // columns j >= N read the valid entry of column N - 1 and meet v_j = 0 (A is
-            // finite), so every load is unconditional; the offsets j and j (j + 1) / 2
-            // of the lane's columns are fixed for the step
-            constexpr int MV = (KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L + G - 1) / G;
+        // two rows per group in flight.  Columns j >= N read the valid entry of column
+        // N - 1 and meet v_j = 0 (A is finite), so every load is unconditional.  The
+        // number of column slots MV is the step's ceil((N - k - 1) / G), chosen from
+        // three compiled widths outside the loops.
+        double pvl = 0.0;
+        auto matvec = [&](auto mvc) {
+            constexpr int MV = decltype(mvc)::value;
             double hr[MV];
             int jc[MV], tj[MV];
 #pragma unroll
@@ -600,12 +605,18 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
                 jc[m] = j < N ? j : N - 1;
                 tj[m] = tri(jc[m], 0);
                 const double h = hv[jc[m]];
-                hr[m] = j < N ? h : 0.0;
+                hr[m] = j < N ? (j == k + 1 ? v1 : h) : 0.0;
             }
             auto row_dot = [&](int i, double (&t)[MV]) {
                 const int rb = tri(i, 0);
 #pragma unroll
                 for (int m = 0; m < MV; ++m) t[m] = A[jc[m] <= i ? rb + jc[m] : tj[m] + i];
+            };
+            auto finish = [&](int i, double acc) {
+                if (gl == 0) {
+                    p[i] = bet * acc;
+                    pvl += bet * acc * (i == k + 1 ? v1 : hv[i]);
+                }
             };
             int i = k + 1 + grp;
             for (; i + ngrp < N; i += 2 * ngrp) {
@@ -623,10 +634,8 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
                     }
                 }
                 const double acc0 = row16_sum(a0 + a1), acc1 = row16_sum(b0 + b1);
-                if (gl == 0) {
-                    p[i] = bet * acc0;
-                    p[i + ngrp] = bet * acc1;
-                }
+                finish(i, acc0);
+                finish(i + ngrp, acc1);
             }
             if (i < N) {
                 double t0[MV];
@@ -637,14 +646,20 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
                     a0 = fma(t0[m], hr[m], a0);
                     if (m + 1 < MV) a1 = fma(t0[m + 1], hr[m + 1], a1);
                 }
-                const double acc0 = row16_sum(a0 + a1);
-                if (gl == 0) p[i] = bet * acc0;
+                finish(i, row16_sum(a0 + a1));
             }
+        };
+        {
+            static_assert(KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L <= 9 * G, "nine column slots cover a row");
+            const int nm = (N - k - 1 + G - 1) / G;
+            if (nm <= 3)
+                matvec(std::integral_constant<int, 3>{});
+            else if (nm <= 5)
+                matvec(std::integral_constant<int, 5>{});
+            else
+                matvec(std::integral_constant<int, 9>{});
         }
-        __syncthreads();
-        double pv = 0.0;
-        for (int i = k + 1 + tid; i < N; i += nt) pv += p[i] * hv[i];
-        const double kk2 = bet * reduce(pv);  // 2 kk
+        const double kk2 = bet * reduce(pvl);  // 2 kk; its barrier publishes p and hv[k + 1]
         // A22 -= v p^T + p v^T - 2 kk v v^T on the lower triangle.  The R = N - k - 1
         // trailing rows are paired, (k + 1 + t, N - 1 - t), so that a pair holds R + 1
         // entries whatever t: a wave per pair, its lanes along the two row segments
