@@ -35,10 +35,78 @@ struct ConvGeo {
 __device__ __forceinline__ int hidden_taps(const ConvGeo& G, int j) { return G.open ? min(G.LW, G.L - j) : G.LW; }
 __device__ __forceinline__ int visible_taps(const ConvGeo& G, int y) { return G.open ? min(G.LW, y + 1) : G.LW; }
 
+// The same pre-activations with the channel count and filter width known at
+// compile time (periodic layer, one bank): every tap of a unit is unrolled, so
+// its LDS loads issue together instead of one per loop trip.  The summation
+// order is that of the general versions, so the results are identical.
+template <typename T, int C_, int LW_>
+__device__ __forceinline__ T preact_hidden_t(const float* Ws, const float* hbs, const uint8_t* v, int L, int k, int i,
+                                             int j)
+{
+    T acc = (T)hbs[k];
+#pragma unroll
+    for (int c = 0; c < C_; ++c)
+#pragma unroll
+        for (int a = 0; a < LW_; ++a) {
+            int ia = i + a;
+            if (ia >= L) ia -= L;
+            const uint8_t* row = v + (c * L + ia) * L;
+            const float* wr = Ws + ((k * C_ + c) * LW_ + a) * LW_;
+#pragma unroll
+            for (int b = 0; b < LW_; ++b) {
+                int jb = j + b;
+                if (jb >= L) jb -= L;
+                if constexpr (sizeof(T) == 4)
+                    acc = fmaf(wr[b], (float)row[jb], acc);
+                else
+                    acc += (double)wr[b] * (double)row[jb];
+            }
+        }
+    return acc;
+}
+
+template <typename T, int C_, int LW_>
+__device__ __forceinline__ T preact_visible_t(const float* Ws, const float* vbs, const uint8_t* h, int K, int L, int c,
+                                              int x, int y)
+{
+    T acc = (T)vbs[c];
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int a = 0; a < LW_; ++a) {
+            int xa = x - a;
+            if (xa < 0) xa += L;
+            const uint8_t* row = h + (k * L + xa) * L;
+            const float* wr = Ws + ((k * C_ + c) * LW_ + a) * LW_;
+#pragma unroll
+            for (int b = 0; b < LW_; ++b) {
+                int yb = y - b;
+                if (yb < 0) yb += L;
+                if constexpr (sizeof(T) == 4)
+                    acc = fmaf(wr[b], (float)row[yb], acc);
+                else
+                    acc += (double)wr[b] * (double)row[yb];
+            }
+        }
+    return acc;
+}
+
+// layers with a compiled form: periodic, one bank, C in {1, 3}, 3 x 3 filters
+__device__ __forceinline__ int compiled_form(const ConvGeo& G)
+{
+    if (G.open || G.ne != 0 || G.dense || G.LW != 3) return 0;
+    return G.C == 3 ? 3 : (G.C == 1 ? 1 : 0);
+}
+
+
 // FP64 hidden pre-activation of unit (k, i, j)
 __device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* hbs, const uint8_t* v,
                                                   const ConvGeo& G, int k, int i, int j)
 {
+    switch (compiled_form(G)) {
+    case 3: return preact_hidden_t<double, 3, 3>(Ws, hbs, v, G.L, k, i, j);
+    case 1: return preact_hidden_t<double, 1, 3>(Ws, hbs, v, G.L, k, i, j);
+    default: break;
+    }
     const int C = G.C, LW = G.LW, L = G.L, nb = hidden_taps(G, j);
     const int bk = G.bank(j);
     const float* Wb = Ws + (size_t)bk * G.bank_size();
@@ -63,6 +131,11 @@ __device__ __forceinline__ double preact_hidden_d(const float* Ws, const float* 
 __device__ __forceinline__ double preact_visible_d(const float* Ws, const float* vbs, const uint8_t* h,
                                                    const ConvGeo& G, int c, int x, int y)
 {
+    switch (compiled_form(G)) {
+    case 3: return preact_visible_t<double, 3, 3>(Ws, vbs, h, G.K, G.L, c, x, y);
+    case 1: return preact_visible_t<double, 1, 3>(Ws, vbs, h, G.K, G.L, c, x, y);
+    default: break;
+    }
     const int K = G.K, C = G.C, LW = G.LW, L = G.L, nb = visible_taps(G, y);
     double acc = (double)vbs[c];
     for (int k = 0; k < K; ++k)
@@ -92,6 +165,11 @@ __device__ __forceinline__ double preact_visible_d(const float* Ws, const float*
 __device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* hbs, const uint8_t* v, const ConvGeo& G,
                                                  int k, int i, int j)
 {
+    switch (compiled_form(G)) {
+    case 3: return preact_hidden_t<float, 3, 3>(Ws, hbs, v, G.L, k, i, j);
+    case 1: return preact_hidden_t<float, 1, 3>(Ws, hbs, v, G.L, k, i, j);
+    default: break;
+    }
     const int C = G.C, LW = G.LW, L = G.L, nb = hidden_taps(G, j);
     const int bk = G.bank(j);
     const float* Wb = Ws + (size_t)bk * G.bank_size();
@@ -114,6 +192,11 @@ __device__ __forceinline__ float preact_hidden_f(const float* Ws, const float* h
 __device__ __forceinline__ float preact_visible_f(const float* Ws, const float* vbs, const uint8_t* h, const ConvGeo& G,
                                                   int c, int x, int y)
 {
+    switch (compiled_form(G)) {
+    case 3: return preact_visible_t<float, 3, 3>(Ws, vbs, h, G.K, G.L, c, x, y);
+    case 1: return preact_visible_t<float, 1, 3>(Ws, vbs, h, G.K, G.L, c, x, y);
+    default: break;
+    }
     const int K = G.K, C = G.C, LW = G.LW, L = G.L, nb = visible_taps(G, y);
     float acc = vbs[c];
     for (int k = 0; k < K; ++k)
