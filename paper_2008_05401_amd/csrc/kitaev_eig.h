@@ -168,6 +168,80 @@ __device__ __forceinline__ int a_at(int i, int j, int N)
     return kFull ? i * N + j : tri(i, j);
 }
 
+// Sturm count at x of the tridiagonal matrix (d, e2 = e^2): the number of sign
+// changes along the leading principal minors p_0 = 1, p_1, ..., p_N, which is the
+// number of eigenvalues below x; p_N = pm 2^xe on return.  kGuard: an exact zero
+// minor is replaced by -2^-100 times its predecessor (so it takes the opposite
+// sign).  Without kGuard no step tests for zero: each step is one dependent FMA,
+// the sign bits of eight minors are shifted into a word and their changes counted
+// with one popcount, and the smallest |p_i| is tracked.  The minors are then those
+// of the guarded count whenever none is zero, and the return value says whether
+// one was (the caller then counts again with kGuard).
+__device__ __forceinline__ uint32_t sign_word(double v) { return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32); }
+
+template <bool kGuard>
+__device__ __forceinline__ bool sturm_count(const lds_f64* d, const lds_f64* e2, int N, double x, int& cnt_out,
+                                            int& xe_out, double& pm_out)
+{
+    double p0 = 1.0, p1 = d[0] - x;
+    int cnt, xe = 0;
+    double zmin = 1.0;
+    uint32_t m = 0;
+    if (kGuard) {
+        if (p1 == 0.0) p1 = -0x1p-100;
+        cnt = p1 < 0.0;
+    } else {
+        zmin = fabs(p1);
+        m = sign_word(p1) >> 31;
+        cnt = (int)m;
+    }
+    int i0 = 1;
+    for (; i0 + 7 < N; i0 += 8) {
+        double dv[8], ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dv[u] = d[i0 + u];
+            ev[u] = e2[i0 + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            double pn = fma(dv[u] - x, p1, -ev[u] * p0);
+            if (kGuard) {
+                if (pn == 0.0) pn = -0x1p-100 * p1;
+                cnt += (pn < 0.0) != (p1 < 0.0);
+            } else {
+                zmin = fmin(zmin, fabs(pn));
+                m = __builtin_amdgcn_alignbit(m, sign_word(pn), 31);  // (m << 1) | sign(pn)
+            }
+            p0 = p1;
+            p1 = pn;
+        }
+        // bits 8..0 of m: signs of p_{i0-1} .. p_{i0+7}
+        if (!kGuard) cnt += __builtin_popcount((m ^ (m >> 1)) & 0xffu);
+        const bool big = fabs(p1) > 0x1p+100, small = fabs(p1) < 0x1p-100;
+        const double f = big ? 0x1p-100 : (small ? 0x1p+100 : 1.0);
+        xe += big ? 100 : (small ? -100 : 0);
+        p0 *= f;
+        p1 *= f;
+    }
+    for (; i0 < N; ++i0) {
+        double pn = fma(d[i0] - x, p1, -e2[i0 - 1] * p0);
+        if (kGuard) {
+            if (pn == 0.0) pn = -0x1p-100 * p1;
+            cnt += (pn < 0.0) != (p1 < 0.0);
+        } else {
+            zmin = fmin(zmin, fabs(pn));
+            cnt += (int)((sign_word(pn) ^ sign_word(p1)) >> 31);
+        }
+        p0 = p1;
+        p1 = pn;
+    }
+    cnt_out = cnt;
+    xe_out = xe;
+    pm_out = p1;
+    return !kGuard && !(zmin > 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // Every eigenvalue of the symmetric tridiagonal matrix (d, e), e2 = e^2, by
 // multisection on the Sturm count, over the whole workgroup: a group of G
@@ -183,9 +257,10 @@ __device__ __forceinline__ int a_at(int i, int j, int N)
 // The count comes from the division-free three-term recurrence
 // p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, p_i = det(T_i - x), one
 // eigenvalue below x per sign change of p_i / p_{i-1}; an exact zero is
-// replaced by -2^-100 p_{i-1} (the sign convention of the ratio form), and the
-// pair is rescaled by 2^-+100 every eight steps to stay in range; the operands
-// of eight steps are read from LDS before the eight dependent steps.  The
+// replaced by -2^-100 p_{i-1} (the sign convention of the ratio form; the fast
+// count of sturm_count leaves the test out and counts again only if a minor was
+// zero), and the pair is rescaled by 2^-+100 every eight steps to stay in range;
+// the operands of eight steps are read from LDS before the eight dependent steps.  The
 // first lane of each group adds log 2cosh(beta eps / 2), the fermion energy,
 // the fluctuation term and the share of eps in the bound B_S (without the factor
 // dlam) to S, Ef, Cf, Bs, and stores eps = sqrt(max(lambda, 0)) to eps_out
@@ -256,39 +331,7 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
             int cnt = 0, xe = 0;
             double pm = 1.0;
             if (live) {
-                double p0 = 1.0, p1 = d[0] - x;
-                if (p1 == 0.0) p1 = -0x1p-100;
-                cnt = p1 < 0.0;
-                int i0 = 1;
-                for (; i0 + 7 < N; i0 += 8) {
-                    double dv[8], ev[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        dv[u] = d[i0 + u];
-                        ev[u] = e2[i0 + u - 1];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        double pn = fma(dv[u] - x, p1, -ev[u] * p0);
-                        if (pn == 0.0) pn = -0x1p-100 * p1;
-                        cnt += (pn < 0.0) != (p1 < 0.0);
-                        p0 = p1;
-                        p1 = pn;
-                    }
-                    const bool big = fabs(p1) > 0x1p+100, small = fabs(p1) < 0x1p-100;
-                    const double f = big ? 0x1p-100 : (small ? 0x1p+100 : 1.0);
-                    xe += big ? 100 : (small ? -100 : 0);
-                    p0 *= f;
-                    p1 *= f;
-                }
-                for (; i0 < N; ++i0) {
-                    double pn = fma(d[i0] - x, p1, -e2[i0 - 1] * p0);
-                    if (pn == 0.0) pn = -0x1p-100 * p1;
-                    cnt += (pn < 0.0) != (p1 < 0.0);
-                    p0 = p1;
-                    p1 = pn;
-                }
-                pm = p1;
+                if (sturm_count<false>(d, e2, N, x, cnt, xe, pm)) sturm_count<true>(d, e2, N, x, cnt, xe, pm);
             }
             // the group's first point with more than idx eigenvalues below it
             const unsigned long long mg = (__ballot(live && cnt > idx) & gmask) >> (gi * G);
