@@ -820,7 +820,65 @@ __device__ __forceinline__ void wave_sync()
 // which every lane reads its entry of column k (symmetry) and the diagonal;
 // v and w go through LDS as before and are read by every lane (broadcast).
 // Lanes <= k and >= N get v_i = w_i = 0, so their rows, and the columns j <= k,
-// stay as they are.
+// stay as they are; step k therefore touches the columns j >= J0 = 8 floor(k / 8)
+// only, and the steps run in stretches of eight with J0 known at compile time.
+template <int NCT, int J0>
+__device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int k, int N, int lane, lds_f64* cb,
+                                                         lds_f64* d, lds_f64* e, lds_f64* vb, lds_f64* wb)
+{
+    if (lane == k) {
+#pragma unroll
+        for (int j = J0; j < NCT; ++j) cb[j] = row[j];
+    }
+    wave_sync();
+    const bool act = lane < N && lane > k;
+    const double x = act ? cb[lane] : 0.0;
+    const double dk = cb[k];
+    const double x0 = cb[k + 1];
+    const double s2 = wave_sum_dpp(x * x);
+    const double rest = s2 - x0 * x0;
+    if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
+        if (lane == 0) {
+            d[k] = dk;
+            e[k] = x0;
+        }
+        wave_sync();
+        return;
+    }
+    const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
+    const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
+    const double vi = lane == k + 1 ? x0 - alpha : x;
+    if (lane < NCT) vb[lane] = vi;
+    wave_sync();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // eight columns at a time: the scheduler may not hoist the loads of later
+    // chunks (their registers would push the rows out of the register file)
+#pragma unroll
+    for (int j = J0; j < NCT; j += 4) {
+        a0 = fma(row[j], vb[j], a0);
+        a1 = fma(row[j + 1], vb[j + 1], a1);
+        a2 = fma(row[j + 2], vb[j + 2], a2);
+        a3 = fma(row[j + 3], vb[j + 3], a3);
+        if ((j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
+    }
+    const double p = act ? bet * ((a0 + a1) + (a2 + a3)) : 0.0;
+    const double kk2 = bet * wave_sum_dpp(p * vi);  // 2 kk
+    const double wi = act ? p - 0.5 * kk2 * vi : 0.0;
+    if (lane < NCT) wb[lane] = wi;
+    wave_sync();
+#pragma unroll
+    for (int j = J0; j < NCT; ++j) {
+        row[j] = fma(-vi, wb[j], row[j]);
+        row[j] = fma(-wi, vb[j], row[j]);
+        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lane == 0) {
+        d[k] = dk;
+        e[k] = alpha;
+    }
+    wave_sync();
+}
+
 template <int NCT>
 __device__ __forceinline__ void kitaev_tridiag_regs(int N, int NS, int lane, lds_f64* A, lds_f64* d, lds_f64* e,
                                                     lds_f64* vb, lds_f64* wb)
@@ -830,58 +888,17 @@ __device__ __forceinline__ void kitaev_tridiag_regs(int N, int NS, int lane, lds
     for (int j = 0; j < NCT; ++j) row[j] = lane < N ? A[lane * NS + j] : 0.0;
     wave_sync();
     lds_f64* cb = A;
-    for (int k = 0; k + 2 < N; ++k) {
-        if (lane == k) {
-#pragma unroll
-            for (int j = 0; j < NCT; ++j) cb[j] = row[j];
-        }
-        wave_sync();
-        const bool act = lane < N && lane > k;
-        const double x = act ? cb[lane] : 0.0;
-        const double dk = cb[k];
-        const double x0 = cb[k + 1];
-        const double s2 = wave_sum_dpp(x * x);
-        const double rest = s2 - x0 * x0;
-        if (!(rest > 1e-300 * (s2 > 1.0 ? s2 : 1.0))) {
-            if (lane == 0) {
-                d[k] = dk;
-                e[k] = x0;
-            }
-            wave_sync();
-            continue;
-        }
-        const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
-        const double bet = 1.0 / (s2 - x0 * alpha);  // 2 / (v^T v)
-        const double vi = lane == k + 1 ? x0 - alpha : x;
-        if (lane < NCT) vb[lane] = vi;
-        wave_sync();
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        // eight columns at a time: the scheduler may not hoist the loads of later
-        // chunks (their registers would push the rows out of the register file)
-#pragma unroll
-        for (int j = 0; j < NCT; j += 4) {
-            a0 = fma(row[j], vb[j], a0);
-            a1 = fma(row[j + 1], vb[j + 1], a1);
-            a2 = fma(row[j + 2], vb[j + 2], a2);
-            a3 = fma(row[j + 3], vb[j + 3], a3);
-            if ((j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
-        }
-        const double p = act ? bet * ((a0 + a1) + (a2 + a3)) : 0.0;
-        const double kk2 = bet * wave_sum_dpp(p * vi);  // 2 kk
-        const double wi = act ? p - 0.5 * kk2 * vi : 0.0;
-        if (lane < NCT) wb[lane] = wi;
-        wave_sync();
-#pragma unroll
-        for (int j = 0; j < NCT; ++j) {
-            row[j] = row[j] - (vi * wb[j] + wi * vb[j]);
-            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-        }
-        if (lane == 0) {
-            d[k] = dk;
-            e[k] = alpha;
-        }
-        wave_sync();
-    }
+    int k = 0;
+    auto stretch = [&](auto j0) {
+        constexpr int J0 = decltype(j0)::value;
+        if constexpr (J0 < NCT)
+            for (; k + 2 < N && k < J0 + 8; ++k) kitaev_tridiag_regs_step<NCT, J0>(row, k, N, lane, cb, d, e, vb, wb);
+    };
+    stretch(std::integral_constant<int, 0>{});
+    stretch(std::integral_constant<int, 8>{});
+    stretch(std::integral_constant<int, 16>{});
+    stretch(std::integral_constant<int, 24>{});
+    stretch(std::integral_constant<int, 32>{});
     // the trailing 2 x 2 block (or the single entry for N = 1)
     if (N >= 2) {
         if (lane == N - 2) {
