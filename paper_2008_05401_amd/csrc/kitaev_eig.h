@@ -815,10 +815,11 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Householder steps of kitaev_tridiag_wave with the rows in registers (NCT
-// columns, N <= NCT <= 40): lane i holds row i of the trailing matrix; at step k
-// lane k writes its row to cb (A's storage, dead once the rows are loaded), from
-// which every lane reads its entry of column k (symmetry) and the diagonal;
-// v and w go through LDS as before and are read by every lane (broadcast).
+// columns, N <= NCT <= 40, NCT a multiple of 4): lane i holds row i of the
+// trailing matrix; at step k lane k writes its row to cb (A's storage, dead once
+// the rows are loaded), from which every lane reads its entry of column k
+// (symmetry) and the diagonal; v and w go through LDS as well and are read by
+// every lane (broadcast).
 // Lanes <= k and >= N get v_i = w_i = 0, so their rows, and the columns j <= k,
 // stay as they are; step k therefore touches the columns j >= J0 = 8 floor(k / 8)
 // only, and the steps run in stretches of eight with J0 known at compile time.
@@ -985,7 +986,8 @@ __device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int o
     //    40 columns (L <= 6) with the rows in registers
     if (NC <= 8) return kitaev_tridiag_regs<8>(N, NS, lane, A, d, e, vb, wb);
     if (NC <= 16) return kitaev_tridiag_regs<16>(N, NS, lane, A, d, e, vb, wb);
-    if (NC <= 32) return kitaev_tridiag_regs<32>(N, NS, lane, A, d, e, vb, wb);
+    if (N <= 28) return kitaev_tridiag_regs<28>(N, NS, lane, A, d, e, vb, wb);
+    if (N <= 36) return kitaev_tridiag_regs<36>(N, NS, lane, A, d, e, vb, wb);
     if (NC <= 40) return kitaev_tridiag_regs<40>(N, NS, lane, A, d, e, vb, wb);
     lds_f64* row = A + (lane < N ? lane : 0) * NS;
     const bool own = lane < N;
