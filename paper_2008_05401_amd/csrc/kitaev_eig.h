@@ -1077,26 +1077,37 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
     lds_f64* vb = ee + N;
     lds_f64* wb = vb + NC;
     lds_f64* eps_l = (lds_f64*)eps_out;
-    if (wid == 0) kitaev_tridiag_wave(v, C, L, open_cols, Jx, Jy, Jz, A, d, e, vb, wb);
-    __syncthreads();
-    for (int i = tid; i + 1 < N; i += blockDim.x) ee[i] = e[i] * e[i];
-    __syncthreads();
-    // Gershgorin bracket of the whole spectrum
-    double glo = 0.0, ghi = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-        glo = fmin(glo, d[i] - r);
-        ghi = fmax(ghi, d[i] + r);
+    if (wid == 0) {
+        kitaev_tridiag_wave(v, C, L, open_cols, Jx, Jy, Jz, A, d, e, vb, wb);
+        // e^2 for the Sturm counts and the Gershgorin bracket of the whole
+        // spectrum (widened to hold 0), lane i taking row i; vb is free again
+        const int lane = tid;
+        double lo = 0.0, hi = 0.0;
+        if (lane < N) {
+            const double r = (lane > 0 ? fabs(e[lane - 1]) : 0.0) + (lane + 1 < N ? fabs(e[lane]) : 0.0);
+            lo = d[lane] - r;
+            hi = d[lane] + r;
+            if (lane + 1 < N) ee[lane] = e[lane] * e[lane];
+        }
+        lo = wave_min_dpp(lo);
+        hi = wave_max_dpp(hi);
+        if (lane == 0) {
+            vb[0] = lo;
+            vb[1] = hi;
+        }
     }
+    __syncthreads();
+    const double glo = vb[0], ghi = vb[1];
     const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
     kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_l, S, Ef, Cf, Bs);
+    block_sum4(S, Ef, Cf, Bs, red);
     KitaevOut o;
-    o.S = block_sum(S, red);
-    o.Ef = block_sum(Ef, red);
-    o.Cf = block_sum(Cf, red);
-    o.B = dlam * block_sum(Bs, red) + (double)(N + 4) * 0x1p-53 * o.S;
+    o.S = S;
+    o.Ef = Ef;
+    o.Cf = Cf;
+    o.B = dlam * Bs + (double)(N + 4) * 0x1p-53 * o.S;
     return o;
 }
 
