@@ -769,27 +769,43 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         d[N - 1] = A[a_at<kFull>(N - 1, N - 1, N)];
     }
     __syncthreads();
+    // 3. the eigenvalues (kitaev_eigs_groups), within the Gershgorin bracket of the
+    //    whole spectrum (widened to hold 0): thread t forms e_i^2 and the interval
+    //    of rows i = t, t + nt, ..., then a wave min / max and one exchange
     lds_f64* ee = hv;  // e^2, hv is free now
-    for (int i = tid; i + 1 < N; i += nt) ee[i] = e[i] * e[i];
-    __syncthreads();
-
-    // 3. the eigenvalues (kitaev_eigs_groups), within the Gershgorin bracket of the whole spectrum
+    double* redg = (double*)red;
     double glo = 0.0, ghi = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-        glo = fmin(glo, d[i] - r);
-        ghi = fmax(ghi, d[i] + r);
+    {
+        double lo = 0.0, hi = 0.0;
+        for (int i = tid; i < N; i += nt) {
+            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+            lo = fmin(lo, d[i] - r);
+            hi = fmax(hi, d[i] + r);
+            if (i + 1 < N) ee[i] = e[i] * e[i];
+        }
+        lo = wave_min_dpp(lo);
+        hi = wave_max_dpp(hi);
+        if (lane == 0) {
+            redg[wid] = lo;
+            redg[nw + wid] = hi;
+        }
+        __syncthreads();
+        for (int w = 0; w < nw; ++w) {
+            glo = fmin(glo, redg[w]);
+            ghi = fmax(ghi, redg[nw + w]);
+        }
+        __syncthreads();
     }
     const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
     kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_out, S, Ef, Cf, Bs);
+    block_sum4(S, Ef, Cf, Bs, redg);
     KitaevOut o;
-    double* redg = (double*)red;
-    o.S = block_sum(S, redg);
-    o.Ef = block_sum(Ef, redg);
-    o.Cf = block_sum(Cf, redg);
-    o.B = dlam * block_sum(Bs, redg) + (double)(N + 4) * 0x1p-53 * o.S;
+    o.S = S;
+    o.Ef = Ef;
+    o.Cf = Cf;
+    o.B = dlam * Bs + (double)(N + 4) * 0x1p-53 * o.S;
     return o;
 }
 
