@@ -876,7 +876,7 @@ __device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int
         a1 = fma(row[j + 1], vb[j + 1], a1);
         a2 = fma(row[j + 2], vb[j + 2], a2);
         a3 = fma(row[j + 3], vb[j + 3], a3);
-        if ((j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
+        if (NCT > 36 && (j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
     }
     const double p = act ? bet * ((a0 + a1) + (a2 + a3)) : 0.0;
     const double kk2 = bet * wave_sum_dpp(p * vi);  // 2 kk
@@ -887,7 +887,7 @@ __device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int
     for (int j = J0; j < NCT; ++j) {
         row[j] = fma(-vi, wb[j], row[j]);
         row[j] = fma(-wi, vb[j], row[j]);
-        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        if (NCT > 36 && (j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     if (lane == 0) {
         d[k] = dk;
