@@ -837,8 +837,8 @@ __device__ __forceinline__ void wave_sync()
 // (symmetry) and the diagonal; v and w go through LDS as well and are read by
 // every lane (broadcast).
 // Lanes <= k and >= N get v_i = w_i = 0, so their rows, and the columns j <= k,
-// stay as they are; step k therefore touches the columns j >= J0 = 8 floor(k / 8)
-// only, and the steps run in stretches of eight with J0 known at compile time.
+// stay as they are; step k therefore touches the columns j >= J0 = 4 floor(k / 4)
+// only, and the steps run in stretches of four with J0 known at compile time.
 template <int NCT, int J0>
 __device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int k, int N, int lane, lds_f64* cb,
                                                          lds_f64* d, lds_f64* e, lds_f64* vb, lds_f64* wb)
@@ -868,14 +868,18 @@ __device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int
     if (lane < NCT) vb[lane] = vi;
     wave_sync();
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    // eight columns at a time: the scheduler may not hoist the loads of later
-    // chunks (their registers would push the rows out of the register file)
+    // v is read once and kept for the update.  Beyond 36 columns, eight columns
+    // at a time: the scheduler may not hoist the loads of later chunks (their
+    // registers would push the rows out of the register file)
+    double vv[NCT];
 #pragma unroll
     for (int j = J0; j < NCT; j += 4) {
-        a0 = fma(row[j], vb[j], a0);
-        a1 = fma(row[j + 1], vb[j + 1], a1);
-        a2 = fma(row[j + 2], vb[j + 2], a2);
-        a3 = fma(row[j + 3], vb[j + 3], a3);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vv[j + t] = vb[j + t];
+        a0 = fma(row[j], vv[j], a0);
+        a1 = fma(row[j + 1], vv[j + 1], a1);
+        a2 = fma(row[j + 2], vv[j + 2], a2);
+        a3 = fma(row[j + 3], vv[j + 3], a3);
         if (NCT > 36 && (j & 7) == 4) __builtin_amdgcn_sched_barrier(0);
     }
     const double p = act ? bet * ((a0 + a1) + (a2 + a3)) : 0.0;
@@ -886,7 +890,7 @@ __device__ __forceinline__ void kitaev_tridiag_regs_step(double (&row)[NCT], int
 #pragma unroll
     for (int j = J0; j < NCT; ++j) {
         row[j] = fma(-vi, wb[j], row[j]);
-        row[j] = fma(-wi, vb[j], row[j]);
+        row[j] = fma(-wi, vv[j], row[j]);
         if (NCT > 36 && (j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     if (lane == 0) {
@@ -909,13 +913,18 @@ __device__ __forceinline__ void kitaev_tridiag_regs(int N, int NS, int lane, lds
     auto stretch = [&](auto j0) {
         constexpr int J0 = decltype(j0)::value;
         if constexpr (J0 < NCT)
-            for (; k + 2 < N && k < J0 + 8; ++k) kitaev_tridiag_regs_step<NCT, J0>(row, k, N, lane, cb, d, e, vb, wb);
+            for (; k + 2 < N && k < J0 + 4; ++k) kitaev_tridiag_regs_step<NCT, J0>(row, k, N, lane, cb, d, e, vb, wb);
     };
     stretch(std::integral_constant<int, 0>{});
+    stretch(std::integral_constant<int, 4>{});
     stretch(std::integral_constant<int, 8>{});
+    stretch(std::integral_constant<int, 12>{});
     stretch(std::integral_constant<int, 16>{});
+    stretch(std::integral_constant<int, 20>{});
     stretch(std::integral_constant<int, 24>{});
+    stretch(std::integral_constant<int, 28>{});
     stretch(std::integral_constant<int, 32>{});
+    stretch(std::integral_constant<int, 36>{});
     // the trailing 2 x 2 block (or the single entry for N = 1)
     if (N >= 2) {
         if (lane == N - 2) {
