@@ -44,6 +44,54 @@
 
 namespace crbm {
 
+// Wave minimum and maximum of a double by the same DPP pattern (exact, so the
+// order does not matter).  Needs the whole wave active.
+__device__ __forceinline__ double wave_min_dpp(double v)
+{
+    v = fmin(v, dpp_f64<0xB1>(v));
+    v = fmin(v, dpp_f64<0x4E>(v));
+    v = fmin(v, dpp_f64<0x141>(v));
+    v = fmin(v, dpp_f64<0x140>(v));
+    return fmin(fmin(readlane_t(v, 0), readlane_t(v, 16)), fmin(readlane_t(v, 32), readlane_t(v, 48)));
+}
+
+__device__ __forceinline__ double wave_max_dpp(double v)
+{
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(readlane_t(v, 0), readlane_t(v, 16)), fmax(readlane_t(v, 32), readlane_t(v, 48)));
+}
+
+// Four workgroup sums at once, each added up exactly as block_sum adds it (so
+// the results are the same), through one exchange in `red` (>= 4 nwaves
+// entries) with two barriers instead of eight.
+__device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& d, double* red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    const double wa = wave_sum(a), wb = wave_sum(b), wc = wave_sum(c), wd = wave_sum(d);
+    if (lane == 0) {
+        red[wid] = wa;
+        red[nw + wid] = wb;
+        red[2 * nw + wid] = wc;
+        red[3 * nw + wid] = wd;
+    }
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        s0 += red[i];
+        s1 += red[nw + i];
+        s2 += red[2 * nw + i];
+        s3 += red[3 * nw + i];
+    }
+    __syncthreads();
+    a = s0;
+    b = s1;
+    c = s2;
+    d = s3;
+}
+
 __device__ __forceinline__ int tri(int i, int j) { return (i * (i + 1) >> 1) + j; }  // j <= i
 __device__ __forceinline__ int tri_s(int i, int j) { return i >= j ? tri(i, j) : tri(j, i); }
 
