@@ -9,7 +9,7 @@ values of M by one-sided Jacobi.  Checked here:
     fields, L = 6, 12, 24, T = 0.005 and 0.05) and is not vacuous at L = 6;
   - with the band forced open (mh_band_min huge) every decision goes through
     the Jacobi route, and trajectories still match the oracle bit for bit;
-  - trajectories at the spec sizes and the lowest temperatures:
+  - trajectories at the benchmarked sizes and the lowest temperatures:
     L = 24 (16 chains x 2 sweeps, T in [0.005, 0.05]) and L = 12 (128 chains
     x 10 sweeps), states and decisions bit-exact, no oracle ties.
 The oracle computes S by one-sided Jacobi too (its own code), in the order of
