@@ -76,7 +76,8 @@ def test_ising_energy_parity(orc, api, L):
     assert np.array_equal(Eg.astype(np.int64), Eo)
 
 
-@pytest.mark.parametrize("C,L", [(3, 1), (3, 2), (3, 3), (1, 4), (3, 6), (3, 9), (3, 12), (1, 12)])
+@pytest.mark.parametrize("C,L", [(3, 1), (3, 2), (3, 3), (1, 4), (1, 5), (3, 6), (3, 7), (1, 8), (3, 9), (3, 12),
+                                 (1, 12)])
 def test_kitaev_weight_parity(orc, api, C, L):
     B = 6
     x = WL.random_states(B, C, L, seed=L + C)
@@ -182,7 +183,7 @@ def test_ising_given_state_and_offset(orc, api):
     _run_pair(orc, api, f, 0, 8, np.full(10, 2.0), seed=3, sweeps=25, state=s0, chain_offset=1000)
 
 
-@pytest.mark.parametrize("C,L", [(3, 6), (1, 6), (3, 3), (3, 2)])
+@pytest.mark.parametrize("C,L", [(3, 6), (1, 6), (3, 3), (3, 2), (1, 4), (3, 5), (1, 7), (3, 8)])
 def test_kitaev_trajectory(orc, api, C, L):
     f = WL.random_filters_with_bias(8, C, 3 if L >= 3 else 2, 0.1, 0.05, seed=C)
     T = WL.kitaev_temperatures(16)
