@@ -255,22 +255,23 @@ __device__ __forceinline__ double dense_visible_d(const float* Ws, const float* 
     return acc;
 }
 
-// F(v) in FP64 over the workgroup (all threads receive it)
-__device__ inline double free_energy_block(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v,
-                                           const ConvGeo& G, double* red)
+// F(v) in FP64: thread t of nt adds its share of the terms (free_energy_part);
+// free_energy_block sums the shares over the workgroup (all threads receive F)
+__device__ inline double free_energy_part(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v,
+                                          const ConvGeo& G, int t, int nt)
 {
     const int L = G.L, LL = L * L;
     double fl = 0.0;
     if (G.dense) {
         const int nv = G.C * LL;
-        for (int k = threadIdx.x; k < G.K; k += blockDim.x) fl -= softplus_d(dense_hidden_d(Ws, hbs, v, nv, k));
-        for (int q = threadIdx.x; q < nv; q += blockDim.x) fl -= (double)vbs[q] * (double)v[q];
-        return block_sum(fl, red);
+        for (int k = t; k < G.K; k += nt) fl -= softplus_d(dense_hidden_d(Ws, hbs, v, nv, k));
+        for (int q = t; q < nv; q += nt) fl -= (double)vbs[q] * (double)v[q];
+        return fl;
     }
-    if (LL >= (int)blockDim.x) {
+    if (LL >= nt) {
         // a lane per site: the K softplus terms in product form, sum_k max(a, 0) +
         // log prod_k (1 + e^{-|a|}), one log per site (each factor in (1, 2], K <= 64)
-        for (int r = threadIdx.x; r < LL; r += blockDim.x) {
+        for (int r = t; r < LL; r += nt) {
             const int i = r / L, j = r - i * L;
             double pos = 0.0, prod = 1.0;
             for (int k = 0; k < G.K; ++k) {
@@ -281,13 +282,19 @@ __device__ inline double free_energy_block(const float* Ws, const float* hbs, co
             fl -= pos + log(prod);
         }
     } else {
-        for (int q = threadIdx.x; q < G.K * LL; q += blockDim.x) {
+        for (int q = t; q < G.K * LL; q += nt) {
             const int k = q / LL, r = q - k * LL, i = r / L, j = r - i * L;
             fl -= softplus_d(preact_hidden_d(Ws, hbs, v, G, k, i, j));
         }
     }
-    for (int q = threadIdx.x; q < G.C * LL; q += blockDim.x) fl -= (double)vbs[q / LL] * (double)v[q];
-    return block_sum(fl, red);
+    for (int q = t; q < G.C * LL; q += nt) fl -= (double)vbs[q / LL] * (double)v[q];
+    return fl;
+}
+
+__device__ inline double free_energy_block(const float* Ws, const float* hbs, const float* vbs, const uint8_t* v,
+                                           const ConvGeo& G, double* red)
+{
+    return block_sum(free_energy_part(Ws, hbs, vbs, v, G, (int)threadIdx.x, (int)blockDim.x), red);
 }
 
 // Ising E/J and M of v (C = 1), over the workgroup; with open_cols the bond

@@ -1135,9 +1135,18 @@ __device__ __noinline__ void kitaev_tridiag_wave(lds_u8c* v, int C, int L, int o
     wave_sync();
 }
 
+// No side work for the waves that wait on the tridiagonal form
+struct KitaevNoSide {
+    __device__ double operator()(int, int) const { return 0.0; }
+};
+
+// Side: work for waves 1..3 while wave 0 tridiagonalises; thread tid - 64 of the
+// 192 calls side(tid - 64, 192) and the returned shares are summed over the
+// workgroup into side_sum (KitaevNoSide: nothing, side_sum untouched).
+template <class Side>
 __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, int L, int open_cols, double Jx,
                                                       double Jy, double Jz, double beta, double* lds, double* eps_out,
-                                                      double* red)
+                                                      double* red, Side side, double& side_sum)
 {
     const int N = L * L, NS = kitaev_wave_stride(N);
     const int tid = threadIdx.x, wid = tid >> 6;
@@ -1150,6 +1159,8 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
     lds_f64* vb = ee + N;
     lds_f64* wb = vb + NC;
     lds_f64* eps_l = (lds_f64*)eps_out;
+    double side_part = 0.0;
+    if (wid != 0) side_part = side(tid - 64, (int)blockDim.x - 64);
     if (wid == 0) {
         kitaev_tridiag_wave(v, C, L, open_cols, Jx, Jy, Jz, A, d, e, vb, wb);
         // e^2 for the Sturm counts and the Gershgorin bracket of the whole
@@ -1176,6 +1187,7 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
     kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_l, S, Ef, Cf, Bs);
     block_sum4(S, Ef, Cf, Bs, red);
+    if constexpr (!std::is_same<Side, KitaevNoSide>::value) side_sum = block_sum(side_part, red);
     KitaevOut o;
     o.S = S;
     o.Ef = Ef;
@@ -1193,8 +1205,11 @@ __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, 
                                                 double Jz, double beta, const KitaevBufs& b, double* red)
 {
     if constexpr (BLOCK == KITAEV_SMALL_NT) {
-        if (L * L <= KITAEV_WAVE_MAX_N)
-            return kitaev_weight_small(v, C, L, open_cols, Jx, Jy, Jz, beta, b.eps, b.eps, red);
+        if (L * L <= KITAEV_WAVE_MAX_N) {
+            double unused = 0.0;
+            return kitaev_weight_small(v, C, L, open_cols, Jx, Jy, Jz, beta, b.eps, b.eps, red, KitaevNoSide{},
+                                       unused);
+        }
     }
     lds_u8c* vl = (lds_u8c*)v;
     if (kitaev_a_in_lds(L))

@@ -252,14 +252,29 @@ __global__ __launch_bounds__(NT) void sweep_generic_kernel(SweepLaunch P)
             src = dst;
         }
         const uint8_t* vp = vb3 + src * C * LL;
-        const double Fp = free_energy_block(Ws, hbs, vbs, vp, G, red);
+        double Fp = 0.0;
         long long Ep = 0, Mp = 0;
         KitaevOut ko{0.0, 0.0, 0.0};
         double* scratch = J.kitA ? J.kitA + (size_t)g * kitaev_chain_doubles(L) : nullptr;
-        if (ising) ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
-        else {
+        if (ising) {
+            Fp = free_energy_block(Ws, hbs, vbs, vp, G, red);
+            ising_em_block(vp, L, J.boundary, redi, Ep, Mp);
+        } else {
             const KitaevBufs kb = kitaev_bufs(kit, scratch, L);
-            ko = kitaev_weight_block<NT>(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
+            bool f_done = false;
+            if constexpr (NT == KITAEV_SMALL_NT) {
+                if (LL <= KITAEV_WAVE_MAX_N) {
+                    // F(x') on waves 1..3 while wave 0 forms the tridiagonal matrix
+                    const auto fside = [=](int ft, int fnt) { return free_energy_part(Ws, hbs, vbs, vp, G, ft, fnt); };
+                    ko = kitaev_weight_small(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb.eps, kb.eps, red, fside,
+                                             Fp);
+                    f_done = true;
+                }
+            }
+            if (!f_done) {
+                Fp = free_energy_block(Ws, hbs, vbs, vp, G, red);
+                ko = kitaev_weight_block<NT>(vp, C, L, J.boundary, J.J0, J.J1, J.J2, beta, kb, red);
+            }
         }
         double lu = 0.0;
         if (tid == 0) {
