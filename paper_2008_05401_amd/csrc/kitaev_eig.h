@@ -321,27 +321,77 @@ __device__ __host__ inline int kitaev_group_size(int N, int nwaves)
     return G;
 }
 
+typedef __attribute__((address_space(3))) int lds_i32;
+
+// doubles of the table of kitaev_eigs_groups for a workgroup of nt threads
+__host__ __device__ inline int kitaev_eig_table_doubles(int nt) { return 2 * nt; }
+
 __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, int N, double glo, double ghi,
                                           double tol, double beta, double dlam, lds_f64* eps_out, double& S,
-                                          double& Ef, double& Cf, double& Bs)
+                                          double& Ef, double& Cf, double& Bs, lds_f64* tab, bool use_tab)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
     const double scale = fmax(fabs(glo), fabs(ghi));
     const int G = kitaev_group_size(N, nw), per_wave = 64 / G, cap = nw * per_wave;
     const int gi = lane / G, sub = lane - gi * G;
     const int gbase = gi * G < 64 ? gi * G : 0;
     const unsigned long long gmask = ((1ull << G) - 1ull) << (gi * G);
     const int rounds = (N + cap - 1) / cap;
+    const double lo0 = glo - (1e-14 * scale + 1e-300), hi0 = ghi + (1e-14 * scale + 1e-300);
+    // With a table (use_tab; kitaev_eig_table_doubles(nt) doubles of LDS at tab,
+    // clear of d, e2 and the N entries of eps_out): one first pass
+    // in which thread t counts at lo0 + (t + 1) h0, h0 = (hi0 - lo0) / (nt + 1),
+    // so that every group starts from the two neighbouring points whose counts
+    // enclose its eigenvalue (their determinants known) instead of the whole
+    // Gershgorin interval
+    const double h0 = (hi0 - lo0) / (double)(nt + 1);
+    lds_i32* tci = (lds_i32*)(tab + nt);
+    if (use_tab) {
+        const double x = lo0 + (double)(tid + 1) * h0;
+        int c = 0, xe = 0;
+        double pm = 1.0;
+        if (sturm_count<false>(d, e2, N, x, c, xe, pm)) sturm_count<true>(d, e2, N, x, c, xe, pm);
+        tab[tid] = pm;
+        tci[2 * tid] = c;
+        tci[2 * tid + 1] = xe;
+        __syncthreads();
+    }
     for (int rd = 0; rd < rounds; ++rd) {
         const int idx = rd * cap + wid * per_wave + gi;
         const bool mine = gi < per_wave && idx < N;
-        double lo = glo - (1e-14 * scale + 1e-300), hi = ghi + (1e-14 * scale + 1e-300);
+        double lo = lo0, hi = hi0;
         // counts and scaled determinants p_N = m 2^x at the bracket's ends (ends
         // not yet evaluated carry no determinant)
         int clo = 0, chi = N;
         double mlo = 0.0, mhi = 0.0;
         int xlo = 0, xhi = 0;
         bool flo = false, fhi = false, sec_failed = false;
+        if (use_tab && mine) {
+            // neighbouring table points a < b with count(a) <= idx < count(b), the
+            // ends standing in for a = -1 (count 0) and b = nt (count N)
+            int a = -1, b = nt;
+            while (b - a > 1) {
+                const int m = (a + b) >> 1;
+                if (tci[2 * m] > idx)
+                    b = m;
+                else
+                    a = m;
+            }
+            if (a >= 0) {
+                lo = lo0 + (double)(a + 1) * h0;
+                clo = tci[2 * a];
+                mlo = tab[a];
+                xlo = tci[2 * a + 1];
+                flo = true;
+            }
+            if (b < nt) {
+                hi = lo0 + (double)(b + 1) * h0;
+                chi = tci[2 * b];
+                mhi = tab[b];
+                xhi = tci[2 * b + 1];
+                fhi = true;
+            }
+        }
         int q = 4;  // the cluster spans w 2^-q; doubled after every hit (the secant error squares)
         bool live = mine;
         for (int it = 0; it < 256; ++it) {
@@ -847,7 +897,9 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
     const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
-    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_out, S, Ef, Cf, Bs);
+    // the table of the first count pass sits in the dead matrix, past the N eps
+    const bool use_tab = !kFull && N * (N + 1) / 2 >= N + kitaev_eig_table_doubles(nt);
+    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_out, S, Ef, Cf, Bs, eps_out + N, use_tab);
     block_sum4(S, Ef, Cf, Bs, redg);
     KitaevOut o;
     o.S = S;
@@ -1185,7 +1237,9 @@ __device__ __noinline__ KitaevOut kitaev_weight_small(const uint8_t* v_, int C, 
     const double tol = 4e-16 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
     const double dlam = kitaev_dlam(N, Jx, Jy, Jz);
     double S = 0.0, Ef = 0.0, Cf = 0.0, Bs = 0.0;
-    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_l, S, Ef, Cf, Bs);
+    // the table of the first count pass sits in the dead matrix, past the N eps
+    const bool use_tab = N * NS >= N + kitaev_eig_table_doubles((int)blockDim.x);
+    kitaev_eigs_groups(d, ee, N, glo, ghi, tol, beta, dlam, eps_l, S, Ef, Cf, Bs, A + N, use_tab);
     block_sum4(S, Ef, Cf, Bs, red);
     if constexpr (!std::is_same<Side, KitaevNoSide>::value) side_sum = block_sum(side_part, red);
     KitaevOut o;
