@@ -298,7 +298,9 @@ __device__ __forceinline__ bool sturm_count(const lds_f64* d, const lds_f64* e2,
 // over), lane `sub` of the group evaluating the point lo + (sub + 1) h,
 // h = (hi - lo) / (G + 1), so the bracket shrinks (G + 1)-fold per step; the
 // group finds its first point whose count exceeds the eigenvalue's index from
-// a ballot.  Once a group's bracket holds its eigenvalue alone, the points
+// a ballot.  With a table, a first pass of one count per thread at evenly
+// spaced points narrows every group's starting bracket to two neighbouring
+// points.  Once a group's bracket holds its eigenvalue alone, the points
 // cluster around the secant root of p_N between the bracket's ends instead
 // (regula falsi on the determinant, every bracket still certified by counts),
 // which ends in a few steps what multisection would take some twenty for.
