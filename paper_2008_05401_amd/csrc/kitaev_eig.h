@@ -804,53 +804,53 @@ __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L
         }
         const double kk2 = bet * reduce(pvl);  // 2 kk; its barrier publishes p and hv[k + 1]
         // A22 -= v p^T + p v^T - 2 kk v v^T on the lower triangle.  The R = N - k - 1
-        // trailing rows are paired, (k + 1 + t, N - 1 - t), so that a pair holds R + 1
-        // entries whatever t: a wave per pair, its lanes along the two row segments
-        // one after the other (the middle row of an odd R alone), so no lane is
-        // given a column beyond its row's end except in a pair's last 64-entry slot
+        // trailing rows are paired, (k + 1 + t, N - 1 - t), a wave per pair; lane q
+        // of 64-entry slot c takes column j = k + 1 + q + 64 c in both rows of the
+        // pair (the short row ends at its diagonal), so p_j and v_j are read once
+        // per step into registers and each entry costs one load and one store
         {
-            // a pair's bookkeeping is wave-uniform (scalar); per lane and 64-entry slot
-            // only the column, the address and the guard of the store are computed.
-            // All slots of a pair (at most three: N <= 144 < 3 x 64) are loaded before
-            // the first store, lanes past a pair's end reading a valid entry that is
-            // not written back.
-            static_assert(KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L < 3 * 64, "a pair must fit three slots");
+            // a pair's bookkeeping is wave-uniform (scalar); all loads of a pair are
+            // issued before its first store, lanes past a row's end reading a valid
+            // entry that is not written back.
+            static_assert(KITAEV_LDS_MAX_L * KITAEV_LDS_MAX_L < 3 * 64, "a row must fit three slots");
             const int R = N - k - 1, npair = (R + 1) / 2;
             const int top = N * (N + 1) / 2 - 1;
-            // slots per pair: ceil((R + 1) / 64), the same for every pair of the step
+            // slots per pair: ceil(R / 64), the longest row of the step
             auto pairs = [&](auto nslot) {
                 constexpr int NSL = decltype(nslot)::value;
+                double pj[NSL], vj[NSL];
+#pragma unroll
+                for (int c = 0; c < NSL; ++c) {
+                    const int jj = k + 1 + lane + 64 * c;
+                    const int jc = jj < N ? jj : N - 1;
+                    pj[c] = p[jc];
+                    vj[c] = hv[jc];
+                }
                 for (int t = __builtin_amdgcn_readfirstlane(wid); t < npair; t += nw) {
                     const int ra = k + 1 + t, rz = N - 1 - t;
-                    const int la = t + 1, len = rz == ra ? la : R + 1;
-                    const int ba = tri(ra, 0) + k + 1, bz = tri(rz, 0) + k + 1 - la;
+                    const int la = t + 1, lz = rz == ra ? 0 : R - t;  // entries of the two rows
+                    const int ba = tri(ra, 0) + k + 1, bz = tri(rz, 0) + k + 1;
                     const double va = hv[ra], vz = hv[rz];
                     const double ca = p[ra] - kk2 * va, cz = p[rz] - kk2 * vz;  // p_i - 2 kk v_i
-                    double a[NSL], pj[NSL], vj[NSL];
-                    int ix[NSL];
+                    double xa[NSL], xz[NSL];
 #pragma unroll
                     for (int c = 0; c < NSL; ++c) {
                         const int q = lane + 64 * c;
-                        const bool in_a = q < la;
-                        const int jj = k + 1 + (in_a ? q : q - la);
-                        const int jc = jj < N ? jj : N - 1;
-                        const int x = (in_a ? ba : bz) + q;
-                        ix[c] = x < top ? x : top;
-                        a[c] = A[ix[c]];
-                        pj[c] = p[jc];
-                        vj[c] = hv[jc];
+                        const int ia = ba + q, iz = bz + q;
+                        xa[c] = A[ia < top ? ia : top];
+                        xz[c] = A[iz < top ? iz : top];
                     }
 #pragma unroll
                     for (int c = 0; c < NSL; ++c) {
                         const int q = lane + 64 * c;
-                        const bool in_a = q < la;
-                        if (q < len) A[ix[c]] = a[c] - ((in_a ? va : vz) * pj[c] + (in_a ? ca : cz) * vj[c]);
+                        if (q < la) A[ba + q] = xa[c] - (va * pj[c] + ca * vj[c]);
+                        if (q < lz) A[bz + q] = xz[c] - (vz * pj[c] + cz * vj[c]);
                     }
                 }
             };
-            if (R + 1 <= 64)
+            if (R <= 64)
                 pairs(std::integral_constant<int, 1>{});
-            else if (R + 1 <= 128)
+            else if (R <= 128)
                 pairs(std::integral_constant<int, 2>{});
             else
                 pairs(std::integral_constant<int, 3>{});
