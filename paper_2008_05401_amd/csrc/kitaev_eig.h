@@ -481,7 +481,9 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
 // v: 0/1 bytes of the proposal, C channels ([3][L][L] = x,y,z bonds, or [1][L][L] = z bonds).
 // open_cols (Sec. IV.B): the x bonds from column L-1 to column 0 are absent.
 // kFull: A stored in full (N x N) rather than as a packed lower triangle.
-template <bool kFull>
+// kNarrow: an instance for 1024-thread callers (128 VGPRs); the other instance
+// serves workgroups of up to 512 threads and so gets 256 registers
+template <bool kFull, bool kNarrow>
 __device__ __noinline__ KitaevOut kitaev_weight_block_t(lds_u8c* v, int C, int L, int open_cols, double Jx, double Jy,
                                                         double Jz, double beta, kit_a_t<kFull>* A, lds_f64* d,
                                                         lds_f64* e, lds_f64* hv, lds_f64* p, lds_f64* red,
@@ -1268,13 +1270,14 @@ __device__ inline KitaevOut kitaev_weight_block(const uint8_t* v, int C, int L, 
         }
     }
     lds_u8c* vl = (lds_u8c*)v;
+    constexpr bool kNarrow = BLOCK > 512;
     if (kitaev_a_in_lds(L))
-        return kitaev_weight_block_t<false>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (lds_f64*)b.A, (lds_f64*)b.d,
-                                            (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p, (lds_f64*)red,
-                                            (lds_f64*)b.eps, nullptr);
-    return kitaev_weight_block_t<true>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (glb_f64*)b.A, (lds_f64*)b.d,
-                                       (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p, (lds_f64*)red, (lds_f64*)b.eps,
-                                       (lds_f64*)b.vw);
+        return kitaev_weight_block_t<false, kNarrow>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (lds_f64*)b.A,
+                                                     (lds_f64*)b.d, (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p,
+                                                     (lds_f64*)red, (lds_f64*)b.eps, nullptr);
+    return kitaev_weight_block_t<true, kNarrow>(vl, C, L, open_cols, Jx, Jy, Jz, beta, (glb_f64*)b.A, (lds_f64*)b.d,
+                                                (lds_f64*)b.e, (lds_f64*)b.hv, (lds_f64*)b.p, (lds_f64*)red,
+                                                (lds_f64*)b.eps, (lds_f64*)b.vw);
 }
 
 // ---------------------------------------------------------------------------
