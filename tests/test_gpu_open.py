@@ -154,7 +154,7 @@ def test_lcrbm_proposal_on_periodic_target(orc, api):
     _run_pair(orc, api, f, 0, 8, np.full(10, 2.2), seed=3, sweeps=25, boundary=0)
 
 
-@pytest.mark.parametrize("C,L,ne", [(1, 6, 3), (3, 6, 1), (1, 4, 2), (3, 3, 1)])
+@pytest.mark.parametrize("C,L,ne", [(1, 6, 3), (3, 6, 1), (1, 4, 2), (3, 3, 1), (3, 5, 2), (1, 7, 3), (3, 8, 1)])
 def test_open_kitaev_trajectory(orc, api, C, L, ne):
     f = rand_lcrbm(6, C, 3 if L >= 3 else 2, ne, seed=C, std=0.1, bias=0.05)
     _run_pair(orc, api, f, 1, L, WL.kitaev_temperatures(12), seed=7, sweeps=6, boundary=1, burnin=1)

@@ -196,6 +196,15 @@ def test_kitaev_l12_trajectory(orc, api):
     _run_pair(orc, api, f, 1, 12, T, seed=1, sweeps=2)
 
 
+@pytest.mark.parametrize("C,L", [(3, 9), (1, 10), (3, 11)])
+def test_kitaev_block_path_trajectory(orc, api, C, L):
+    """L = 9..11: the packed-LDS eigen-step of 512-thread workgroups at the
+    other slot counts of its rank-2 update."""
+    f = WL.random_filters(8, C, 3, 0.1, seed=L)
+    T = WL.kitaev_temperatures(4)
+    _run_pair(orc, api, f, 1, L, T, seed=2, sweeps=2)
+
+
 def test_many_jobs_equal_alone(orc, api):
     fa = WL.random_filters(4, 1, 3, 0.2, seed=1)
     fb = WL.random_filters(8, 1, 5, 0.05, seed=2)
