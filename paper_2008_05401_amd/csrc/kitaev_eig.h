@@ -468,11 +468,13 @@ __device__ inline void kitaev_eigs_groups(const lds_f64* d, const lds_f64* e2, i
             const double lam = 0.5 * (lo + hi);
             const double eps = sqrt(lam > 0.0 ? lam : 0.0);
             eps_out[idx] = eps;
-            const double xv = 0.5 * beta * eps;
-            S += log2cosh_d(xv);
+            const double xv = 0.5 * beta * eps;  // >= 0
+            // log 2cosh(xv) = xv + log1p(e) with e = exp(-2 xv), the steps of
+            // log2cosh_d; 1 / cosh^2(xv) = 4 e / (1 + e)^2 from the same e
+            const double em = exp(-2.0 * xv), op = 1.0 + em;
+            S += xv + log1p(em);
             Ef -= 0.5 * eps * tanh(xv);
-            const double ch = cosh(xv);
-            Cf += (xv * xv) / (ch * ch);
+            Cf += (xv * xv) * (4.0 * em / (op * op));
             Bs += kitaev_bound_term(lam, beta, dlam);
         }
     }
