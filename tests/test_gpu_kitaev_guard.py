@@ -42,7 +42,7 @@ def S_of(eps, T):
     return float(np.sum(np.abs(x) + np.log1p(np.exp(-2 * np.abs(x)))))
 
 
-@pytest.mark.parametrize("L,C", [(6, 3), (12, 3), (24, 1)])
+@pytest.mark.parametrize("L,C", [(5, 1), (6, 3), (8, 3), (9, 1), (12, 3), (24, 1)])
 def test_bound_holds_against_lapack(orc, api, L, C):
     T = np.array([0.005, 0.05, 0.005, 0.05])
     u = WL.random_states(4, C, L, seed=100 + L)
